@@ -1,0 +1,363 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix:
+hand-derived encodings, published SplitMix64 outputs, brute-force set
+membership, the Bloom filter occupancy and false-positive laws (Section 2.1,
+Lemma 4.1), Algorithm 2 versus the per-document definition, streaming
+insertion, strand invariance and folding (Section 5.3)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import twin
+from tests import _ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+P61 = (1 << 61) - 1
+
+
+# ---------------------------------------------------------------- encoding
+def test_encoding_golden():
+    n = 0
+    for line in open(os.path.join(GOLDEN, "kmer_canonical.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        w, c = line.split()
+        got = oracle.window(w.encode())
+        if c == "-":
+            assert got is None, w
+        else:
+            assert got == int(c.translate(str.maketrans("ACGT", "0123")), 4), w
+        n += 1
+    assert n >= 10
+
+
+def test_revcomp_identities():
+    rng = np.random.default_rng(0)
+    xs = rng.integers(0, 1 << 62, size=2000, dtype=np.uint64)
+    rcs = _ref.revcomp_np(xs)
+    for x, r in zip(xs[:300].tolist(), rcs[:300].tolist()):
+        assert oracle.revcomp(x) == r
+        assert oracle.revcomp(r) == x
+        assert oracle.canon(x) == oracle.canon(r) == min(x, r)
+        assert x != r  # odd k: no 31-mer is its own reverse complement
+
+
+def test_generator_codes_vs_oracle_windows():
+    dm = gen.DocModel(seed=5, n_docs=1, length=2000)
+    s = dm.doc(0)
+    codes = dm.window_codes(0)
+    canon = _ref.canon_np(codes)
+    for p in range(0, 1970, 37):
+        assert oracle.window(s, p) == int(canon[p])
+    assert np.array_equal(_ref.seq_terms(s), canon)
+
+
+# ---------------------------------------------------------------- hashing
+def test_parameters_drawn_from_published_splitmix_outputs():
+    v = [int(l) for l in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt"))
+         if l.strip() and not l.startswith("#")]
+    o = oracle.Oracle(10, 4, 1, 1 << 20, 1, 1234567)
+    p = o.params()
+    assert int(p["pa"][0]) == 1 + v[0] % (P61 - 1)
+    assert int(p["pb"][0]) == v[1] % P61
+    assert int(p["Alo"][0]) == v[2] and int(p["Ahi"][0]) == v[3] and int(p["Clo"][0]) == v[4]
+
+
+def test_phi_two_universal():
+    """Carter-Wegman: for fixed d1 != d2, over random seeds, the collision
+    probability is about 1/B; every cell gets about K/B documents."""
+    B, trials, hits = 16, 4000, 0
+    for s in range(trials):
+        o = oracle.Oracle(1000, B, 1, 64, 1, 10_000 + s, alloc_bits=False)
+        hits += o.phi(0, 3) == o.phi(0, 977)
+    assert abs(hits / trials - 1 / B) < 4 * math.sqrt((1 / B) * (1 - 1 / B) / trials)
+    o = oracle.Oracle(100_000, 100, 3, 64, 1, 7, alloc_bits=False)
+    for r in range(3):
+        cnt = np.bincount([o.phi(r, d) for d in range(0, 100_000, 7)], minlength=100)
+        exp = cnt.sum() / 100
+        chi2 = ((cnt - exp) ** 2 / exp).sum()
+        assert chi2 < 99 + 6 * math.sqrt(2 * 99)
+
+
+def test_h_strongly_universal_small_range():
+    """Multiply-add-shift: for fixed x != y, over random parameters, the pair
+    (h(x), h(y)) is uniform on [m]^2; with m = 16 collisions occur with
+    probability 1/16 and each value with probability 1/16."""
+    m, trials = 16, 6000
+    coll, val = 0, np.zeros(m, dtype=np.int64)
+    x, y = 0x123456789ABCDEF & ((1 << 62) - 1), 0x3ABCDEF012345678 & ((1 << 62) - 1)
+    for s in range(trials):
+        o = oracle.Oracle(10, 2, 1, m, 1, 50_000 + s, alloc_bits=False)
+        hx, hy = o.h(0, 0, x), o.h(0, 0, y)
+        coll += hx == hy
+        val[hx] += 1
+    assert abs(coll / trials - 1 / m) < 4 * math.sqrt((1 / m) * (1 - 1 / m) / trials)
+    exp = trials / m
+    assert ((val - exp) ** 2 / exp).sum() < 15 + 6 * math.sqrt(30)
+
+
+def test_h_positions_uniform_and_in_range():
+    o = oracle.Oracle(10, 2, 2, 1000, 2, 3, alloc_bits=False)
+    rng = np.random.default_rng(1)
+    xs = rng.integers(0, 1 << 62, size=20000, dtype=np.uint64).tolist()
+    pos = np.array([o.h(1, 1, x) for x in xs])
+    assert pos.min() >= 0 and pos.max() < 1000
+    cnt = np.bincount(pos // 50, minlength=20)
+    exp = 1000
+    assert ((cnt - exp) ** 2 / exp).sum() < 19 + 6 * math.sqrt(38)
+
+
+def test_twin_agrees_on_hashes_and_queries():
+    K, B, R, m, eta = 12, 3, 2, 4096, 2
+    o = oracle.Oracle(K, B, R, m, eta, 77)
+    t = twin.Twin(K, B, R, m, eta, 77)
+    rng = np.random.default_rng(2)
+    for x in rng.integers(0, 1 << 62, size=50, dtype=np.uint64).tolist():
+        for r in range(R):
+            for j in range(eta):
+                assert o.h(r, j, x) == t.h(r, j, x)
+    for d in range(K):
+        for r in range(R):
+            assert o.phi(r, d) == t.phi(r, d)
+    dm = gen.DocModel(seed=8, n_docs=K, length=120, docs_per_anc=3, mu_lo=0.05, mu_hi=0.05)
+    for d in range(K):
+        s = dm.doc(d)
+        o.insert_seq(d, s)
+        t.insert_terms(d, twin.kmer_terms(s))
+    bits = o.bits()
+    for r in range(R):
+        for b in range(B):
+            got = set(np.nonzero(np.unpackbits(bits[r, b].view(np.uint8), bitorder="little")[:m])[0].tolist())
+            assert got == t.bfu[r][b]
+    for d in range(0, K, 2):
+        s = dm.doc(d, 10, 40)
+        assert _ref.bits_to_ids(o.query_seq(s), K) == t.query_terms(twin.kmer_terms(s))
+
+
+# ---------------------------------------------------------------- structure
+def _small_index(K=40, B=5, R=3, m=1 << 26, eta=2, L=300, seed=21):
+    dm = gen.DocModel(seed=seed, n_docs=K, length=L, docs_per_anc=4, mu_lo=0.03, mu_hi=0.03)
+    o = oracle.Oracle(K, B, R, m, eta, seed + 1)
+    docs = dm.docs(0, K)
+    o.build_docs(docs, L, 0, K, nthreads=4)
+    table = _ref.KmerTable({d: _ref.seq_terms(docs[d * L:(d + 1) * L].tobytes()) for d in range(K)})
+    return dm, o, table
+
+
+def test_exact_partition_brute_force():
+    """With m far above the number of inserted terms, Bloom filters make no
+    errors w.h.p., so the answer must equal RAMBO over exact sets: d is kept
+    iff, in every repetition, the union of the sets of d's cell holds every
+    term (Section 3: union within a repetition, intersection across). The
+    truth (documents containing every term) must be inside it."""
+    K, B, R = 40, 5, 3
+    dm, o, table = _small_index(K=K, B=B, R=R)
+    phis = o.phis()
+    cell_sets = {(r, b): set().union(*[table.sets[d] for d in range(K) if phis[r, d] == b])
+                 for r in range(R) for b in range(B)}
+    rng = np.random.default_rng(3)
+    n_nonempty = 0
+    for q in range(200):
+        d = int(rng.integers(K))
+        st = int(rng.integers(0, 300 - 40))
+        s = dm.doc(d, st, int(rng.integers(31, 40)))
+        Q = set(_ref.seq_terms(s).tolist())
+        ex = {e for e in range(K) if all(Q <= cell_sets[(r, phis[r, e])] for r in range(R))}
+        truth = table.truth_seq(np.array(sorted(Q), dtype=np.uint64), K)
+        got = _ref.bits_to_ids(o.query_seq(s), K)
+        assert truth <= ex
+        assert got == ex, (q, d)
+        n_nonempty += len(got) > 0
+    assert n_nonempty == 200
+    # single terms, through both the definition and Algorithm 2
+    for x in list(table.sets[0])[:50]:
+        ex = {e for e in range(K) if all(x in cell_sets[(r, phis[r, e])] for r in range(R))}
+        assert _ref.bits_to_ids(o.query_kmer(x), K) == ex
+        assert _ref.bits_to_ids(o.query_kmer(x, oracle.MODE_ALG2), K) == ex
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = gen.workload(1)
+    o = oracle.Oracle(w.K, w.B, w.R, w.m, w.eta, w.index_seed)
+    docs = w.docs.docs(0, w.docs.n_docs)
+    L = w.docs.length
+    o.build_docs(docs, L, 0, w.docs.n_docs)
+    table = _ref.KmerTable({d: _ref.seq_terms(docs[d * L:(d + 1) * L].tobytes()) for d in range(w.K)})
+    q, src = gen.kmer_queries(w.docs, w.kmer_qseed, w.n_kmer_queries, 0.5)
+    res = o.query_kmers(q, oracle.MODE_DEF)
+    return w, o, docs, table, q, src, res
+
+
+def test_c1_zero_false_negatives(c1):
+    w, o, docs, table, q, src, res = c1
+    cq = _ref.canon_np(q)
+    for i in range(q.size):
+        truth = set(table.docs_with(int(cq[i])).tolist())
+        got = _ref.bits_to_ids(res[i], w.K)
+        assert truth <= got
+        if src[i] >= 0:
+            assert int(src[i]) in truth
+
+
+def test_c1_alg2_equals_definition(c1):
+    w, o, docs, table, q, src, res = c1
+    res2 = o.query_kmers(q[:3000], oracle.MODE_ALG2)
+    assert np.array_equal(res2, res[:3000])
+    # padding bits above K stay zero
+    assert np.all(res[:, -1] >> np.uint64(w.K & 63) == 0)
+
+
+def test_c1_bloom_occupancy_law(c1):
+    """Section 2.1: after inserting n distinct keys with eta hashes into m
+    bits, the expected number of set bits is m (1 - (1 - 1/m)^(eta n))."""
+    w, o, docs, table, q, src, res = c1
+    phis = o.phis()
+    for r in range(w.R):
+        for b in range(w.B):
+            n_b = len(set().union(*[table.sets[d] for d in range(w.K) if phis[r, d] == b]))
+            exp = w.m * (1 - (1 - 1 / w.m) ** (w.eta * n_b))
+            q_ = exp / w.m
+            sd = math.sqrt(w.m * q_ * (1 - q_))
+            assert abs(o.bfu_popcount(r, b) - exp) < 6 * sd, (r, b)
+
+
+def test_c1_false_positive_law(c1):
+    """Fresh terms (absent from every document): document d is reported with
+    probability prod_r fill(r, phi_r(d))^eta (Section 2.1 per BFU, independent
+    repetitions), and on average about p^R (Lemma 4.1 with V = 0)."""
+    w, o, docs, table, q, src, res = c1
+    cq = _ref.canon_np(q)
+    fresh = np.nonzero((src < 0) & (table.multiplicity(cq) == 0))[0]
+    assert fresh.size > 4500
+    phis = o.phis()
+    fill = np.array([[o.bfu_popcount(r, b) / w.m for b in range(w.B)] for r in range(w.R)])
+    pdoc = np.prod([fill[r, phis[r]] ** w.eta for r in range(w.R)], axis=0)
+    bits = np.unpackbits(res[fresh].view(np.uint8), axis=1, bitorder="little")[:, :w.K]
+    observed = bits.sum()
+    expected = fresh.size * pdoc.sum()
+    assert abs(observed - expected) < max(8 * math.sqrt(expected), 0.08 * expected), (observed, expected)
+    p = (fill ** w.eta).mean()
+    lemma = fresh.size * w.K * p ** w.R
+    assert abs(observed - lemma) < 0.2 * lemma, (observed, lemma)
+
+
+def test_c1_lemma_4_1_multiplicity_one(c1):
+    """Present terms of multiplicity V = 1 (i.i.d. documents): a document that
+    does not hold the term is reported iff, in every repetition, it shares the
+    true document's cell or its own BFU gives a false positive. Sharp form
+    with the realised cells and fills; Lemma 4.1's F_p on average."""
+    w, o, docs, table, q, src, res = c1
+    cq = _ref.canon_np(q)
+    mult = table.multiplicity(cq)
+    pres = np.nonzero((src >= 0) & (mult == 1))[0]
+    phis = o.phis()
+    fill = np.array([[o.bfu_popcount(r, b) / w.m for b in range(w.B)] for r in range(w.R)])
+    obs = exp = 0.0
+    for i in pres:
+        t = int(src[i])
+        pr = np.ones(w.K)
+        for r in range(w.R):
+            same = phis[r] == phis[r, t]
+            pr *= np.where(same, 1.0, fill[r, phis[r]] ** w.eta)
+        pr[t] = 0
+        got = _ref.bits_to_ids(res[i], w.K) - {t}
+        obs += len(got)
+        exp += pr.sum()
+    assert abs(obs - exp) < max(8 * math.sqrt(exp), 0.08 * exp), (obs, exp)
+    p = (fill ** w.eta).mean()
+    Fp = (p * (1 - 1 / w.B) + 1 - (1 - 1 / w.B)) ** w.R
+    lemma = pres.size * (w.K - 1) * Fp
+    assert abs(obs - lemma) < 0.35 * lemma, (obs, lemma)
+
+
+# ---------------------------------------------------------------- invariants
+def test_streaming_insert_equals_batch_build_and_order_independent():
+    K, B, R, m, eta, L = 30, 4, 3, 1 << 16, 2, 500
+    dm = gen.DocModel(seed=31, n_docs=K, length=L, docs_per_anc=5, mu_lo=0.02, mu_hi=0.02)
+    docs = dm.docs(0, K)
+    full = oracle.Oracle(K, B, R, m, eta, 9)
+    full.build_docs(docs, L, 0, K)
+    part = oracle.Oracle(K, B, R, m, eta, 9)
+    part.build_docs(docs, L, 0, 20)
+    probe = dm.doc(25, 100, 60)
+    before = _ref.bits_to_ids(part.query_seq(probe), K)
+    for d in range(20, K):
+        part.insert_seq(d, docs[d * L:(d + 1) * L].tobytes())
+    assert np.array_equal(part.bits(), full.bits())
+    after = _ref.bits_to_ids(part.query_seq(probe), K)
+    assert 25 in after and 25 not in before
+    perm = oracle.Oracle(K, B, R, m, eta, 9)
+    for d in np.random.default_rng(4).permutation(K):
+        perm.insert_seq(int(d), docs[d * L:(d + 1) * L].tobytes())
+    assert np.array_equal(perm.bits(), full.bits())
+    # the same document given as k-mer codes (either strand) sets the same bits
+    km = oracle.Oracle(K, B, R, m, eta, 9)
+    for d in range(K):
+        codes = dm.window_codes(d)
+        if d % 2:
+            codes = _ref.revcomp_np(codes)
+        km.insert_kmers(d, codes)
+    assert np.array_equal(km.bits(), full.bits())
+
+
+def test_bfu_is_union_of_document_filters():
+    """Section 3: BFU(r, b) is the Bloom filter of the union of its
+    documents' sets, i.e. the OR of the single-document filters."""
+    K, B, R, m, eta, L = 16, 3, 2, 1 << 14, 2, 300
+    dm = gen.DocModel(seed=41, n_docs=K, length=L)
+    full = oracle.Oracle(K, B, R, m, eta, 5)
+    acc = np.zeros((R, B, full.wpb), dtype=np.uint64)
+    for d in range(K):
+        s = dm.doc(d)
+        full.insert_seq(d, s)
+        one = oracle.Oracle(K, B, R, m, eta, 5)
+        one.insert_seq(d, s)
+        acc |= one.bits()
+    assert np.array_equal(acc, full.bits())
+
+
+def test_strand_invariance_and_empty_queries():
+    dm, o, table = _small_index(K=20, B=4, R=2, m=1 << 16, L=400, seed=51)
+    rng = np.random.default_rng(5)
+    for _ in range(30):
+        d = int(rng.integers(20))
+        s = dm.doc(d, int(rng.integers(0, 300)), int(rng.integers(31, 100)))
+        a = o.query_seq(s)
+        assert np.array_equal(a, o.query_seq(_ref.revcomp_seq(s)))
+        assert np.array_equal(a, o.query_seq(s.lower()))
+        assert np.array_equal(a, o.query_seq(s, oracle.MODE_ALG2, early_exit=True))
+        assert np.array_equal(a, o.query_seq(s, oracle.MODE_ALG2, early_exit=False))
+    everyone = _ref.ids_to_bits(range(20), 20)
+    for s in (b"", b"ACGT" * 7, b"N" * 100, b"ACGTN" * 20):
+        assert np.array_equal(o.query_seq(s), everyone)
+        assert np.array_equal(o.query_seq(s, oracle.MODE_ALG2), everyone)
+
+
+def test_invalid_inputs_rejected():
+    o = oracle.Oracle(10, 2, 2, 1024, 2, 1)
+    with pytest.raises(ValueError):
+        o.insert_kmers(0, np.array([1 << 62], dtype=np.uint64))
+    with pytest.raises(ValueError):
+        o.insert_kmers(10, np.array([5], dtype=np.uint64))
+    assert not o.bits().any()
+
+
+def test_fold_equals_rebuild_with_half_the_cells():
+    """Section 5.3 folding: OR-ing BFU(r, b + B/2) onto BFU(r, b) gives the
+    index built directly with B/2 cells (same seeds, phi mod B/2)."""
+    K, B, R, m, eta, L = 40, 8, 3, 1 << 16, 2, 400
+    dm = gen.DocModel(seed=61, n_docs=K, length=L, docs_per_anc=4, mu_lo=0.02, mu_hi=0.02)
+    docs = dm.docs(0, K)
+    big = oracle.Oracle(K, B, R, m, eta, 13)
+    big.build_docs(docs, L, 0, K)
+    half = oracle.Oracle(K, B // 2, R, m, eta, 13)
+    half.build_docs(docs, L, 0, K)
+    f = big.fold()
+    assert np.array_equal(f.bits(), half.bits())
+    s = dm.doc(7, 50, 80)
+    assert np.array_equal(f.query_seq(s), half.query_seq(s))
+    assert _ref.bits_to_ids(big.query_seq(s), K) <= _ref.bits_to_ids(f.query_seq(s), K)
