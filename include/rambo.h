@@ -1,0 +1,239 @@
+/*
+ * rambo.h -- C ABI of librambo.so, a RAMBO index (Repeated And Merged BloOm
+ * filter; Gupta et al., SIGMOD 2021) resident in the HBM of one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The index is an R x B array of Bloom filters of m bits ("BFUs", Section 3):
+ * document d belongs to BFU(r, phi_r(d)) in each repetition r; BFU(r, b) is
+ * the Bloom filter (Section 2.1) of the union of the k-mer sets of its
+ * documents. Terms are canonical 31-mers (Section 5.1). A query term is
+ * reported for d iff BFU(r, phi_r(d)) passes its Bloom test in every
+ * repetition (Section 3.3, Algorithm 2); a sequence query ANDs the answers of
+ * all its terms (Section 3.3.1).
+ *
+ * Conventions shared by every entry point:
+ *  - k = 31. A k-mer value is a 2-bit code, A=0 C=1 G=2 T=3, first base in
+ *    the two most significant of the 62 low bits; values >= 4^31 are not
+ *    k-mers. The library canonicalises every value it is given
+ *    (min(code, reverse complement)), so either strand may be passed.
+ *  - Sequences are bytes; A/C/G/T in either case are bases; a window of 31
+ *    bytes holding any other byte is not a term and is skipped.
+ *  - Results are K-bit bitsets of W = ceil(K / 64) uint64 words per query:
+ *    document d is bit (d & 63) of word (d >> 6); bits >= K are zero.
+ *  - Hash functions (fixed by definition, shared with no other code): with P
+ *    = 2^61 - 1 and SplitMix64 seeded by `seed`, drawn in the order below,
+ *      phi_r(d)    = ((a_r d + b_r) mod P) mod B           (Carter-Wegman)
+ *      h_{r,j}(x)  = floor(m * hi64((A_{r,j} x + C_{r,j}) mod 2^128) / 2^64)
+ *    where for r < R: a_r = 1 + next mod (P - 1), b_r = next mod P; then for
+ *    r < R, j < eta: A = next | next << 64 (low word first), C likewise.
+ *  - Pointers named "device" are HIP device pointers (e.g. torch tensors on
+ *    the GPU); `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream). Entry points that take a stream only enqueue work and return;
+ *    the caller orders them (same stream, or events). Device buffers stay
+ *    owned by the caller and must stay valid until the enqueued work ends.
+ *  - Every entry point returns a status (RAMBO_OK = 0, negative on error)
+ *    and records a message readable with rambo_last_error() on the calling
+ *    thread. Errors detected on the GPU (invalid k-mer values in a device
+ *    batch) are counted and reported by the next rambo_sync().
+ *  - Queries may run concurrently on one handle. Insertions and queries must
+ *    be ordered by the caller; a query that overlaps an insertion is
+ *    unsupported.
+ */
+#ifndef RAMBO_H
+#define RAMBO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rambo_s rambo_t;
+
+enum {
+    RAMBO_OK = 0,
+    RAMBO_EINVAL = -1,  /* bad argument or invalid k-mer value */
+    RAMBO_ENOMEM = -2,  /* device or host allocation failed */
+    RAMBO_EDEVICE = -3, /* HIP runtime error */
+    RAMBO_ETRUNC = -4,  /* id output too small (see rambo_query_seqs_ids) */
+    RAMBO_EBUSY = -5,   /* server queue full / admission refused */
+};
+
+/* Query execution forms for rambo_query_seqs. */
+enum {
+    RAMBO_MODE_PLAIN = 0,   /* one launch, one wavefront per read */
+    RAMBO_MODE_BATCHED = 1, /* persistent launch over (read, k-mer tile) work
+                               items, replayed from a captured HIP graph */
+};
+
+/* Resolve strategies (Section 3.3, Algorithm 2: union of the documents of
+ * positive BFUs per repetition, intersection across repetitions). */
+enum {
+    RAMBO_RESOLVE_AUTO = 0,      /* pick per query from the cell sizes */
+    RAMBO_RESOLVE_DENSE = 1,     /* every document d tests its R cells */
+    RAMBO_RESOLVE_CANDIDATE = 2, /* documents of positive repetition-0 cells
+                                    are tested in the other repetitions */
+};
+
+/* Limits: 1 <= R <= 8, 1 <= eta <= 8, 1 <= B <= 8192, 1 <= K < 2^32,
+ * 1 <= m <= 2^40. */
+#define RAMBO_MAX_R 8
+#define RAMBO_MAX_ETA 8
+#define RAMBO_MAX_B 8192
+
+/* ---------------------------------------------------------------------- */
+/* Lifetime and errors                                                     */
+/* ---------------------------------------------------------------------- */
+
+/* Allocate an empty index of K documents (ids 0..K-1; K is the capacity, so
+ * documents can be added later, Section 3.2 "conducive to updates"), R
+ * repetitions of B BFUs of m bits each, eta Bloom hash functions, on the
+ * current HIP device. The index is a bit-sliced array rows[R][m] of B-bit
+ * rows, each padded to a power of two >= 32 bits, zeroed. Returns NULL on
+ * error (RAMBO_EINVAL for out-of-range parameters, RAMBO_ENOMEM if the
+ * device cannot hold the index); see rambo_last_error(). The handle owns all
+ * its device memory. */
+rambo_t *rambo_create(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed);
+
+/* Free the index and everything the handle owns. NULL-safe. Waits for the
+ * handle's own outstanding work. */
+void rambo_destroy(rambo_t *h);
+
+/* Message and status of the last failing call on this thread. */
+const char *rambo_last_error(void);
+int rambo_last_status(void);
+
+/* Wait for all work the handle enqueued on `stream` (NULL: the null stream)
+ * and report GPU-side input errors counted since the previous call:
+ * RAMBO_EINVAL if any k-mer value >= 4^31 was skipped by an insertion or
+ * answered with an empty result by a query. */
+int rambo_sync(rambo_t *h, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Introspection                                                           */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    uint64_t K, m, seed;
+    uint32_t B, R, eta;
+    uint32_t row_words;  /* 32-bit words per row: power of two >= ceil(B/32) */
+    uint64_t W;          /* result words per query */
+    uint64_t index_bytes;/* R * m * row_words * 4 */
+    void *rows;          /* device pointer to rows[R][m][row_words] (uint32) */
+} rambo_layout_t;
+
+int rambo_layout(const rambo_t *h, rambo_layout_t *out);
+uint64_t rambo_result_words(const rambo_t *h);
+uint64_t rambo_index_bytes(const rambo_t *h);
+
+/* The derived hash parameters (host arrays: pa, pb of R entries; Alo, Ahi,
+ * Clo, Chi of R*eta entries, index r*eta + j). */
+int rambo_hash_params(const rambo_t *h, uint64_t *pa, uint64_t *pb, uint64_t *Alo, uint64_t *Ahi,
+                      uint64_t *Clo, uint64_t *Chi);
+
+/* phi_r(d) for every r < R, d < K into a host array phi[r * K + d]. */
+int rambo_phi_table(const rambo_t *h, uint32_t *phi);
+
+/* BFU(r, b) as a plain m-bit Bloom filter: bit p of host word out[p / 64]
+ * (ceil(m/64) words) is the bit of cell b in row p of repetition r.
+ * Synchronous. */
+int rambo_dump_bfu(rambo_t *h, uint32_t r, uint32_t b, uint64_t *out);
+
+/* Copy `bytes` bytes of the raw row array, starting at byte `offset`, to the
+ * host buffer `dst`. Synchronous. */
+int rambo_copy_rows(rambo_t *h, uint64_t offset, uint64_t bytes, void *dst);
+
+/* ---------------------------------------------------------------------- */
+/* Construction (Algorithm 1)                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Insert document doc_id given n k-mer values (host array, either strand,
+ * duplicates allowed). Every term goes into BFU(r, phi_r(doc_id)) for every
+ * r. Synchronous. RAMBO_EINVAL (and nothing inserted) if doc_id >= K or any
+ * value >= 4^31. Inserting twice is harmless (bits are ORed). */
+int rambo_insert(rambo_t *h, uint64_t doc_id, const uint64_t *kmers, uint64_t n);
+
+/* Insert n_docs documents from device arrays: document i has id doc_ids[i]
+ * and k-mers kmers[kmer_offsets[i] .. kmer_offsets[i+1]) (offsets
+ * non-decreasing, n_docs+1 entries). Enqueued on `stream`. Values >= 4^31 are
+ * skipped and reported by rambo_sync(); ids >= K are skipped likewise. */
+int rambo_insert_batch(rambo_t *h, const uint64_t *doc_ids, const uint64_t *kmer_offsets,
+                       const uint64_t *kmers, uint64_t n_docs, void *stream);
+
+/* Insert n_docs documents given as sequences (device arrays): document i has
+ * id doc_ids[i] and bytes seqs[offsets[i] .. offsets[i+1]); its terms are its
+ * valid 31-windows (Figure 1). Extraction runs on the GPU. Enqueued on
+ * `stream`. */
+int rambo_insert_seqs(rambo_t *h, const uint64_t *doc_ids, const uint8_t *seqs,
+                      const uint64_t *offsets, uint64_t n_docs, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Queries (Algorithm 2, Section 3.3.1)                                    */
+/* ---------------------------------------------------------------------- */
+
+/* n single k-mer queries (device array). out (device, n * W words) receives
+ * one K-bit result per query. A value >= 4^31 gets an empty result and is
+ * reported by rambo_sync(). Plain one-batch kernel. Enqueued on `stream`. */
+int rambo_query_kmers(rambo_t *h, const uint64_t *kmers, uint64_t n, uint64_t *out, void *stream);
+
+/* n sequence queries: read i is seqs[offsets[i] .. offsets[i+1]) (device
+ * arrays; offsets non-decreasing). out (device, n * W words) receives, per
+ * read, the documents that hold every term of the read. A read with no valid
+ * window gets every document (the vacuous "every term is in the BFU" of
+ * Algorithm 2). Once the running AND of some repetition is empty the read is
+ * finished (Section 3.3.1: the first FALSE is conclusive). Uses the handle's
+ * mode (rambo_set_mode). Enqueued on `stream`. */
+int rambo_query_seqs(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
+                     uint64_t *out, void *stream);
+
+/* As rambo_query_seqs, but results are ascending document-id lists: read i's
+ * ids are ids[id_offsets[i] .. id_offsets[i+1]) (device arrays, id_offsets
+ * has n+1 entries, ids has room for ids_cap entries). Uses `scratch` (device,
+ * n * W words) for the bitsets. Synchronous on `stream` (it must learn the
+ * total). If the total exceeds ids_cap, returns RAMBO_ETRUNC with
+ * id_offsets filled (id_offsets[n] = required capacity) and ids untouched. */
+int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
+                         uint64_t *scratch, uint32_t *ids, uint64_t *id_offsets, uint64_t ids_cap,
+                         void *stream);
+
+/* Select the execution form of rambo_query_seqs (RAMBO_MODE_*). */
+int rambo_set_mode(rambo_t *h, int mode);
+
+/* Select the resolve strategy (RAMBO_RESOLVE_*); all give identical bits. */
+int rambo_set_resolve(rambo_t *h, int resolve);
+
+/* Disable (0) or enable (1, default) early exit in sequence queries; the
+ * results are identical either way (only the work differs). */
+int rambo_set_early_exit(rambo_t *h, int on);
+
+/* Device counter that sequence queries add the number of issued row probes
+ * to (NULL disables counting). Owned by the caller; one uint64. */
+int rambo_set_probe_counter(rambo_t *h, uint64_t *device_counter);
+
+/* Launch shape of the batched form (RAMBO_MODE_BATCHED). */
+typedef struct {
+    int seg;          /* 32-bit row words one lane reads: 1, 2 or 4 (row split
+                         over row_words / seg lanes) */
+    int tile;         /* windows per work item, a multiple of 64 */
+    int waves_per_cu; /* resident waves per compute unit of the persistent grid */
+    int wpb;          /* waves per workgroup: 1, 2 or 4 */
+    int grab;         /* work items taken per queue access */
+    int tuned;        /* output of rambo_get_tune: 1 once chosen or set */
+} rambo_tune_t;
+
+/* Search the batched form's launch shape on a representative batch (device
+ * arrays as in rambo_query_seqs; `out` receives the batch's results). The
+ * first batched query of a handle runs this search itself unless the
+ * environment sets RAMBO_TUNE=off; RAMBO_TUNE_CACHE names a file that keeps
+ * chosen shapes across processes. Synchronous on `stream`. */
+int rambo_autotune(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n, uint64_t *out,
+                   void *stream);
+int rambo_get_tune(const rambo_t *h, rambo_tune_t *out);
+int rambo_set_tune(rambo_t *h, const rambo_tune_t *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAMBO_H */

@@ -1,0 +1,11 @@
+"""RAMBO (Repeated And Merged BloOm filter) hot path on AMD Instinct MI355X.
+
+The index and every step of building and querying it run in hand-written HIP
+kernels behind the C ABI of ``librambo.so`` (``include/rambo.h``); this
+package is the thin Python binding (``rambo.py``) and its build script.
+"""
+from .rambo import (EBUSY, EDEVICE, EINVAL, ENOMEM, ETRUNC, MODE_BATCHED, MODE_PLAIN, OK, RESOLVE_AUTO,
+                    RESOLVE_CANDIDATE, RESOLVE_DENSE, Rambo, RamboError, Tune, check_offsets, lib)
+
+__all__ = ["Rambo", "RamboError", "Tune", "lib", "check_offsets", "MODE_PLAIN", "MODE_BATCHED", "RESOLVE_AUTO",
+           "RESOLVE_DENSE", "RESOLVE_CANDIDATE", "OK", "EINVAL", "ENOMEM", "EDEVICE", "ETRUNC", "EBUSY"]

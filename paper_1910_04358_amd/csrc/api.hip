@@ -1,0 +1,344 @@
+// C ABI of librambo: handle lifetime, hash parameters, introspection, and
+// the entry points that validate arguments and dispatch to the kernels.
+#include <cstdio>
+#include <cstring>
+
+#include "rambo_int.h"
+
+namespace rambo {
+
+static thread_local std::string g_err;
+static thread_local int g_status = RAMBO_OK;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    g_status = status;
+    return status;
+}
+
+int ok() { return RAMBO_OK; }
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), sequential form.
+static uint64_t splitmix_next(uint64_t &s) {
+    s += 0x9E3779B97F4A7C15ULL;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+static constexpr uint64_t P61 = (1ULL << 61) - 1;
+
+// Draw the partition and Bloom hash parameters, then phi_r(d) for all d.
+static void derive_hashes(rambo_s *h) {
+    uint64_t s = h->seed;
+    h->pa.resize(h->R);
+    h->pb.resize(h->R);
+    for (uint32_t r = 0; r < h->R; r++) {
+        h->pa[r] = 1 + splitmix_next(s) % (P61 - 1);
+        h->pb[r] = splitmix_next(s) % P61;
+    }
+    const uint32_t E = h->R * h->eta;
+    h->Alo.resize(E); h->Ahi.resize(E); h->Clo.resize(E); h->Chi.resize(E);
+    for (uint32_t i = 0; i < E; i++) {
+        h->Alo[i] = splitmix_next(s);
+        h->Ahi[i] = splitmix_next(s);
+        h->Clo[i] = splitmix_next(s);
+        h->Chi[i] = splitmix_next(s);
+    }
+    // phi_r(d) = ((a_r d + b_r) mod P) mod B, Carter-Wegman over the Mersenne
+    // prime P; a_r d + b_r < 2^122 fits 128 bits.
+    h->phi.resize((size_t)h->R * h->K);
+    for (uint32_t r = 0; r < h->R; r++) {
+        for (uint64_t d = 0; d < h->K; d++) {
+            unsigned __int128 v = (unsigned __int128)h->pa[r] * d + h->pb[r];
+            h->phi[(size_t)r * h->K + d] = (uint32_t)((uint64_t)(v % P61) % h->B);
+        }
+    }
+}
+
+static void free_device(rambo_s *h) {
+    if (h->rows) (void)hipFree(h->rows);
+    if (h->d_hp) (void)hipFree(h->d_hp);
+    if (h->d_phi) (void)hipFree(h->d_phi);
+    if (h->d_boff) (void)hipFree(h->d_boff);
+    if (h->d_bdoc) (void)hipFree(h->d_bdoc);
+    if (h->d_invalid) (void)hipFree(h->d_invalid);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
+    h->rows = nullptr;
+}
+
+static int upload_tables(rambo_s *h) {
+    HashParams hp;
+    memset(&hp, 0, sizeof hp);
+    for (uint32_t i = 0; i < h->R * h->eta; i++) {
+        hp.Alo[i] = h->Alo[i]; hp.Ahi[i] = h->Ahi[i];
+        hp.Clo[i] = h->Clo[i]; hp.Chi[i] = h->Chi[i];
+    }
+    HIP_CHECK(hipMalloc(&h->d_hp, sizeof hp));
+    HIP_CHECK(hipMemcpy(h->d_hp, &hp, sizeof hp, hipMemcpyHostToDevice));
+
+    std::vector<uint16_t> phi16(h->phi.size());
+    for (size_t i = 0; i < phi16.size(); i++) phi16[i] = (uint16_t)h->phi[i];
+    HIP_CHECK(hipMalloc(&h->d_phi, phi16.size() * 2));
+    HIP_CHECK(hipMemcpy(h->d_phi, phi16.data(), phi16.size() * 2, hipMemcpyHostToDevice));
+
+    // documents grouped by cell, per repetition (Algorithm 2's DocIDs(M[b, r])),
+    // with cell offsets relative to the repetition's slice of bdoc
+    std::vector<uint32_t> boff((size_t)h->R * (h->B + 1), 0), bdoc((size_t)h->R * h->K);
+    for (uint32_t r = 0; r < h->R; r++) {
+        uint32_t *off = &boff[(size_t)r * (h->B + 1)];
+        const uint32_t *ph = &h->phi[(size_t)r * h->K];
+        for (uint64_t d = 0; d < h->K; d++) off[ph[d] + 1]++;
+        for (uint32_t b = 0; b < h->B; b++) off[b + 1] += off[b];
+        std::vector<uint32_t> fill(h->B, 0);
+        for (uint64_t d = 0; d < h->K; d++) {
+            const uint32_t b = ph[d];
+            bdoc[(size_t)r * h->K + off[b] + fill[b]++] = (uint32_t)d;
+        }
+        // absolute offsets into bdoc
+        for (uint32_t b = 0; b <= h->B; b++) off[b] += (uint32_t)((size_t)r * h->K);
+    }
+    HIP_CHECK(hipMalloc(&h->d_boff, boff.size() * 4));
+    HIP_CHECK(hipMemcpy(h->d_boff, boff.data(), boff.size() * 4, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMalloc(&h->d_bdoc, bdoc.size() * 4));
+    HIP_CHECK(hipMemcpy(h->d_bdoc, bdoc.data(), bdoc.size() * 4, hipMemcpyHostToDevice));
+    return RAMBO_OK;
+}
+
+}  // namespace rambo
+
+using namespace rambo;
+
+RAMBO_API const char *rambo_last_error(void) { return g_err.c_str(); }
+RAMBO_API int rambo_last_status(void) { return g_status; }
+
+RAMBO_API rambo_t *rambo_create(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed) {
+    if (K == 0 || K >= (1ULL << 32) || B == 0 || B > RAMBO_MAX_B || R == 0 || R > RAMBO_MAX_R || eta == 0 ||
+        eta > RAMBO_MAX_ETA || m == 0 || m > (1ULL << 40)) {
+        fail(RAMBO_EINVAL, "rambo_create: parameters out of range (K=%llu B=%u R=%u m=%llu eta=%u)",
+             (unsigned long long)K, B, R, (unsigned long long)m, eta);
+        return nullptr;
+    }
+    auto *h = new rambo_s();
+    h->K = K; h->B = B; h->R = R; h->m = m; h->eta = eta; h->seed = seed;
+    uint32_t need = (B + 31) / 32, rw = 1, lg = 0;
+    while (rw < need) { rw <<= 1; lg++; }
+    h->RW = rw;
+    h->log2RW = lg;
+    h->W = (K + 63) / 64;
+    h->rows_bytes = (uint64_t)R * m * rw * 4;
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+        fail(RAMBO_EDEVICE, "rambo_create: no usable HIP device");
+        delete h;
+        return nullptr;
+    }
+    derive_hashes(h);
+    if (hipMalloc(&h->rows, h->rows_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(RAMBO_ENOMEM, "rambo_create: cannot allocate %llu bytes of index on the device",
+             (unsigned long long)h->rows_bytes);
+        h->rows = nullptr;
+        free_device(h);
+        delete h;
+        return nullptr;
+    }
+    int st = RAMBO_OK;
+    if (hipMemset(h->rows, 0, h->rows_bytes) != hipSuccess) st = fail(RAMBO_EDEVICE, "rambo_create: memset failed");
+    if (st == RAMBO_OK) st = upload_tables(h);
+    if (st == RAMBO_OK && hipMalloc(&h->d_invalid, sizeof(unsigned long long)) != hipSuccess)
+        st = fail(RAMBO_ENOMEM, "rambo_create: counter allocation failed");
+    if (st == RAMBO_OK && hipMemset(h->d_invalid, 0, sizeof(unsigned long long)) != hipSuccess)
+        st = fail(RAMBO_EDEVICE, "rambo_create: memset failed");
+    if (st == RAMBO_OK && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess)
+        st = fail(RAMBO_EDEVICE, "rambo_create: stream creation failed");
+    if (st != RAMBO_OK) {
+        free_device(h);
+        delete h;
+        return nullptr;
+    }
+    return h;
+}
+
+RAMBO_API void rambo_destroy(rambo_t *h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    drop_graphs(h);
+    free_device(h);
+    delete h;
+}
+
+RAMBO_API int rambo_sync(rambo_t *h, void *stream) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_sync: null handle");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_CHECK(hipStreamSynchronize(s));
+    unsigned long long bad = 0;
+    HIP_CHECK(hipMemcpy(&bad, h->d_invalid, sizeof bad, hipMemcpyDeviceToHost));
+    if (bad) {
+        HIP_CHECK(hipMemset(h->d_invalid, 0, sizeof bad));
+        return fail(RAMBO_EINVAL, "%llu invalid k-mer values or document ids were skipped", bad);
+    }
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_layout(const rambo_t *h, rambo_layout_t *out) {
+    if (!h || !out) return fail(RAMBO_EINVAL, "rambo_layout: null argument");
+    out->K = h->K; out->m = h->m; out->seed = h->seed;
+    out->B = h->B; out->R = h->R; out->eta = h->eta;
+    out->row_words = h->RW;
+    out->W = h->W;
+    out->index_bytes = h->rows_bytes;
+    out->rows = h->rows;
+    return RAMBO_OK;
+}
+
+RAMBO_API uint64_t rambo_result_words(const rambo_t *h) { return h ? h->W : 0; }
+RAMBO_API uint64_t rambo_index_bytes(const rambo_t *h) { return h ? h->rows_bytes : 0; }
+
+RAMBO_API int rambo_hash_params(const rambo_t *h, uint64_t *pa, uint64_t *pb, uint64_t *Alo, uint64_t *Ahi,
+                                uint64_t *Clo, uint64_t *Chi) {
+    if (!h || !pa || !pb || !Alo || !Ahi || !Clo || !Chi) return fail(RAMBO_EINVAL, "rambo_hash_params: null argument");
+    memcpy(pa, h->pa.data(), h->R * 8);
+    memcpy(pb, h->pb.data(), h->R * 8);
+    const size_t E = (size_t)h->R * h->eta * 8;
+    memcpy(Alo, h->Alo.data(), E); memcpy(Ahi, h->Ahi.data(), E);
+    memcpy(Clo, h->Clo.data(), E); memcpy(Chi, h->Chi.data(), E);
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_phi_table(const rambo_t *h, uint32_t *phi) {
+    if (!h || !phi) return fail(RAMBO_EINVAL, "rambo_phi_table: null argument");
+    memcpy(phi, h->phi.data(), h->phi.size() * 4);
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_dump_bfu(rambo_t *h, uint32_t r, uint32_t b, uint64_t *out) {
+    if (!h || !out || r >= h->R || b >= h->B) return fail(RAMBO_EINVAL, "rambo_dump_bfu: bad argument");
+    const uint64_t words = (h->m + 63) / 64;
+    uint64_t *d = nullptr;
+    HIP_CHECK(hipMalloc(&d, words * 8));
+    int st = launch_dump_bfu(h, r, b, d, h->aux);
+    if (st == RAMBO_OK && hipStreamSynchronize(h->aux) != hipSuccess) st = fail(RAMBO_EDEVICE, "rambo_dump_bfu: kernel failed");
+    if (st == RAMBO_OK && hipMemcpy(out, d, words * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        st = fail(RAMBO_EDEVICE, "rambo_dump_bfu: copy failed");
+    (void)hipFree(d);
+    return st;
+}
+
+RAMBO_API int rambo_copy_rows(rambo_t *h, uint64_t offset, uint64_t bytes, void *dst) {
+    if (!h || !dst || offset > h->rows_bytes || bytes > h->rows_bytes - offset)
+        return fail(RAMBO_EINVAL, "rambo_copy_rows: range outside the index");
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemcpy(dst, (const char *)h->rows + offset, bytes, hipMemcpyDeviceToHost));
+    return RAMBO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// construction
+// ---------------------------------------------------------------------------
+RAMBO_API int rambo_insert(rambo_t *h, uint64_t doc_id, const uint64_t *kmers, uint64_t n) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_insert: null handle");
+    if (doc_id >= h->K) return fail(RAMBO_EINVAL, "rambo_insert: doc_id %llu >= K", (unsigned long long)doc_id);
+    if (n == 0) return RAMBO_OK;
+    if (!kmers) return fail(RAMBO_EINVAL, "rambo_insert: null k-mer array");
+    for (uint64_t i = 0; i < n; i++)
+        if (kmers[i] >> 62)
+            return fail(RAMBO_EINVAL, "rambo_insert: value %llu at %llu is not a 31-mer code",
+                        (unsigned long long)kmers[i], (unsigned long long)i);
+    uint64_t *d = nullptr;
+    HIP_CHECK(hipMalloc(&d, n * 8 + 3 * 8));
+    const uint64_t meta[3] = {doc_id, 0, n};  // doc_ids[1], offsets[2]
+    int st = RAMBO_OK;
+    if (hipMemcpyAsync(d, kmers, n * 8, hipMemcpyHostToDevice, h->aux) != hipSuccess ||
+        hipMemcpyAsync(d + n, meta, sizeof meta, hipMemcpyHostToDevice, h->aux) != hipSuccess)
+        st = fail(RAMBO_EDEVICE, "rambo_insert: copy failed");
+    if (st == RAMBO_OK) st = launch_build_kmers(h, d, d + n + 1, d + n, 1, h->aux);
+    if (hipStreamSynchronize(h->aux) != hipSuccess && st == RAMBO_OK) st = fail(RAMBO_EDEVICE, "rambo_insert: kernel failed");
+    (void)hipFree(d);
+    return st;
+}
+
+RAMBO_API int rambo_insert_batch(rambo_t *h, const uint64_t *doc_ids, const uint64_t *kmer_offsets,
+                                 const uint64_t *kmers, uint64_t n_docs, void *stream) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_insert_batch: null handle");
+    if (n_docs == 0) return RAMBO_OK;
+    if (!doc_ids || !kmer_offsets || !kmers) return fail(RAMBO_EINVAL, "rambo_insert_batch: null array");
+    return launch_build_kmers(h, kmers, kmer_offsets, doc_ids, n_docs, (hipStream_t)stream);
+}
+
+RAMBO_API int rambo_insert_seqs(rambo_t *h, const uint64_t *doc_ids, const uint8_t *seqs, const uint64_t *offsets,
+                                uint64_t n_docs, void *stream) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_insert_seqs: null handle");
+    if (n_docs == 0) return RAMBO_OK;
+    if (!doc_ids || !seqs || !offsets) return fail(RAMBO_EINVAL, "rambo_insert_seqs: null array");
+    return launch_build_seqs(h, seqs, offsets, doc_ids, n_docs, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// queries
+// ---------------------------------------------------------------------------
+RAMBO_API int rambo_query_kmers(rambo_t *h, const uint64_t *kmers, uint64_t n, uint64_t *out, void *stream) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_query_kmers: null handle");
+    if (n == 0) return RAMBO_OK;
+    if (!kmers || !out) return fail(RAMBO_EINVAL, "rambo_query_kmers: null array");
+    return launch_query_kmers(h, kmers, n, out, (hipStream_t)stream);
+}
+
+RAMBO_API int rambo_query_seqs(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n, uint64_t *out,
+                               void *stream) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_query_seqs: null handle");
+    if (n == 0) return RAMBO_OK;
+    if (!seqs || !offsets || !out) return fail(RAMBO_EINVAL, "rambo_query_seqs: null array");
+    if (h->mode == RAMBO_MODE_BATCHED) return query_seqs_batched(h, seqs, offsets, n, out, (hipStream_t)stream);
+    return launch_query_seqs_plain(h, seqs, offsets, n, out, (hipStream_t)stream, default_seg(h->RW));
+}
+
+RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
+                                   uint64_t *scratch, uint32_t *ids, uint64_t *id_offsets, uint64_t ids_cap,
+                                   void *stream) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null handle");
+    if (!id_offsets) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null id_offsets");
+    if (n > 0 && (!scratch || !seqs || !offsets)) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null array");
+    if (n > 0) {
+        int st = rambo_query_seqs(h, seqs, offsets, n, scratch, stream);
+        if (st != RAMBO_OK) return st;
+    }
+    return launch_ids(h, scratch, n, ids, id_offsets, ids_cap, (hipStream_t)stream);
+}
+
+RAMBO_API int rambo_set_mode(rambo_t *h, int mode) {
+    if (!h || (mode != RAMBO_MODE_PLAIN && mode != RAMBO_MODE_BATCHED)) return fail(RAMBO_EINVAL, "rambo_set_mode: bad mode");
+    h->mode = mode;
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_set_resolve(rambo_t *h, int resolve) {
+    if (!h || resolve < RAMBO_RESOLVE_AUTO || resolve > RAMBO_RESOLVE_CANDIDATE)
+        return fail(RAMBO_EINVAL, "rambo_set_resolve: bad strategy");
+    std::lock_guard<std::mutex> g(h->mu);
+    h->resolve = resolve;
+    drop_graphs(h);
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_set_early_exit(rambo_t *h, int on) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_set_early_exit: null handle");
+    std::lock_guard<std::mutex> g(h->mu);
+    h->early_exit = on ? 1 : 0;
+    drop_graphs(h);
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_set_probe_counter(rambo_t *h, uint64_t *device_counter) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_set_probe_counter: null handle");
+    std::lock_guard<std::mutex> g(h->mu);
+    h->probe_counter = (unsigned long long *)device_counter;
+    drop_graphs(h);
+    return RAMBO_OK;
+}

@@ -1,0 +1,463 @@
+// Batched sequence queries: one persistent launch over a work queue of
+// (read, tile of windows) items, replayed from a captured HIP graph, with a
+// launch shape chosen by an autotuner.
+//
+// Work order: first tile of every read, then the remaining tiles of all reads
+// in read order. Reads are short (a few hundred bases) and most end after
+// their first tile (Section 3.3.1: the first FALSE is conclusive), so later
+// tiles mostly find their read already dead and skip their probes. Long reads
+// are spread over many waves; their tiles AND into a per-read mask in global
+// memory (AND is associative and commutative, so the order does not matter)
+// and the wave that finishes a read's last tile resolves it.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "rambo_int.h"
+
+namespace rambo {
+
+struct BatchBufs {
+    uint32_t *rmask;             // [n][R * RW] running AND per read
+    uint32_t *done;              // [n] finished tiles per read
+    uint64_t *extra;             // [n] tiles beyond the first, per read
+    uint64_t *extra_off;         // [n + 1] exclusive scan of extra
+    unsigned long long *head;    // queue position
+};
+
+struct BatchGraph {
+    uint64_t n = 0;
+    BatchBufs bb{};
+    void *mem = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+__device__ __forceinline__ uint64_t n_windows(uint64_t beg, uint64_t end) {
+    return end >= beg + 31 ? end - beg - 30 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_batch_prep(const uint64_t *__restrict__ offs, uint64_t n, uint32_t mw,
+                                                    uint32_t tile, BatchBufs bb) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *bb.head = 0;
+    if (i >= n) return;
+    const uint64_t beg = offs[i], end = offs[i + 1];
+    const uint64_t nw = n_windows(beg, end > beg ? end : beg);
+    const uint64_t tiles = nw ? (nw + tile - 1) / tile : 1;
+    bb.extra[i] = tiles - 1;
+    bb.done[i] = 0;
+    for (uint32_t w = 0; w < mw; w++) bb.rmask[i * mw + w] = 0xFFFFFFFFu;
+}
+
+// exclusive scan (single workgroup), off[n] = total
+__global__ __launch_bounds__(1024) void k_scan_u64(const uint64_t *__restrict__ v, uint64_t n,
+                                                   uint64_t *__restrict__ off) {
+    __shared__ uint64_t part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint64_t per = (n + 1023) / 1024, lo = t * per, hi = min(n, lo + per);
+    uint64_t sum = 0;
+    for (uint64_t i = lo; i < hi; i++) sum += v[i];
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        const uint64_t x = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint64_t run = part[t] - sum;
+    for (uint64_t i = lo; i < hi; i++) {
+        off[i] = run;
+        run += v[i];
+    }
+    if (t == 1023) off[n] = part[1023];
+}
+
+// largest i < n with off[i] <= u, by a 64-way search (one load per lane per round)
+__device__ __forceinline__ uint64_t find_read(const uint64_t *off, uint64_t n, uint64_t u, uint32_t lane) {
+    uint64_t lo = 0, hi = n;  // invariant: off[lo] <= u, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint64_t step = (hi - lo + 63) / 64;
+        const uint64_t idx = lo + (uint64_t)lane * step;
+        const bool pred = idx < hi && off[idx] <= u;
+        const uint32_t k = (uint32_t)__popcll(__ballot(pred)) - 1;  // pred holds on a prefix of lanes
+        lo = lo + (uint64_t)k * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t load_coherent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// some repetition of the read's global running mask is already empty
+__device__ __forceinline__ bool read_dead(const Index &ix, const uint32_t *rm, uint32_t lane) {
+    bool dead = false;
+    for (uint32_t r = 0; r < ix.R; r++) {
+        uint32_t o = 0;
+        for (uint32_t w = lane; w < ix.RW; w += 64) o |= load_coherent(rm + r * ix.RW + w);
+        dead |= __ballot(o != 0) == 0;
+    }
+    return dead;
+}
+
+template <int SEG, int G>
+__global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__restrict__ seqs,
+                                                    const uint64_t *__restrict__ offs, uint64_t n,
+                                                    uint64_t *__restrict__ out, BatchBufs bb, QueryOpts opt,
+                                                    int use_res, uint32_t tile, uint32_t grab) {
+    extern __shared__ uint64_t smem64[];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t mw = ix.R * ix.RW;
+    const uint32_t mwords = (mw + 1) & ~1u;
+    const uint32_t per_wave = mwords + (use_res ? 2 * ix.W : 0);
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * per_wave;
+    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + mwords) : nullptr;
+
+    const uint64_t total = n + bb.extra_off[n];
+    uint64_t issued = 0;
+    for (;;) {
+        uint64_t t0 = 0;
+        if (lane == 0) t0 = atomicAdd(bb.head, (unsigned long long)grab);
+        t0 = __shfl(t0, 0);
+        if (t0 >= total) break;
+        const uint64_t t1 = min(total, t0 + grab);
+        for (uint64_t t = t0; t < t1; t++) {
+            uint64_t i, c;
+            if (t < n) {
+                i = t;
+                c = 0;
+            } else {
+                const uint64_t u = t - n;
+                i = find_read(bb.extra_off, n, u, lane);
+                c = 1 + (u - bb.extra_off[i]);
+            }
+            const uint64_t beg = offs[i];
+            uint64_t end = offs[i + 1];
+            if (end < beg) end = beg;
+            const uint64_t nwin = n_windows(beg, end);
+            const uint64_t ntiles = nwin ? (nwin + tile - 1) / tile : 1;
+            uint32_t *rm = bb.rmask + i * mw;
+
+            bool skip = c > 0 && opt.early_exit && read_dead(ix, rm, lane);
+            if (!skip) {
+                Seg<SEG> acc[MAXR];
+                set_ones(acc);
+                const uint64_t w_hi = min(nwin, (c + 1) * (uint64_t)tile);
+                for (uint64_t w = c * (uint64_t)tile; w < w_hi; w += 64) {
+                    const uint64_t p = beg + w + lane;
+                    const uint32_t c0 = p < end ? seqs[p] : 0u;
+                    const uint32_t c1 = (lane < 30 && p + 64 < end) ? seqs[p + 64] : 0u;
+                    const Window wv = extract_windows(c0, c1, lane);
+                    const bool valid = wv.valid && (w + lane < w_hi);
+                    Seg<SEG> cm[MAXR];
+                    probe_chunk<SEG, G>(ix, wv, valid, lane, cm);
+#pragma unroll
+                    for (int r = 0; r < MAXR; r++)
+#pragma unroll
+                        for (int s = 0; s < SEG; s++) acc[r].w[s] &= cm[r].w[s];
+                    issued += __popcll(__ballot(valid));
+                    if (opt.early_exit && some_rep_empty<SEG, G>(acc, ix.R)) break;
+                }
+                if (lane < (uint32_t)G) {
+#pragma unroll
+                    for (int r = 0; r < MAXR; r++)
+                        if (r < (int)ix.R)
+#pragma unroll
+                            for (int s = 0; s < SEG; s++)
+                                if (acc[r].w[s] != 0xFFFFFFFFu) atomicAnd(rm + r * ix.RW + lane * SEG + s, acc[r].w[s]);
+                }
+            }
+            __threadfence();
+            uint32_t prev = 0;
+            if (lane == 0) prev = atomicAdd(bb.done + i, 1u);
+            prev = __shfl(prev, 0);
+            if (prev + 1 == ntiles) {
+                // last tile of read i: every other tile's AND is visible
+                __threadfence();
+                for (uint32_t w = lane; w < mw; w += 64) M[w] = load_coherent(rm + w);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                bool empty = false;
+                for (uint32_t r = 0; r < ix.R; r++) {
+                    uint32_t o = 0;
+                    for (uint32_t w = lane; w < ix.RW; w += 64) o |= M[r * ix.RW + w];
+                    empty |= __ballot(o != 0) == 0;
+                }
+                uint64_t *o = out + i * ix.W;
+                if (empty) write_zeros(o, ix.W, lane);
+                else resolve(ix, M, res, o, lane, opt.rmode);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.R * ix.eta));
+}
+
+static constexpr uint32_t kMaxLds = 64 * 1024;
+
+#define RAMBO_DISPATCH_SEG_G_B(SEGV, GV, ...)                              \
+    switch ((SEGV) * 1000 + (GV)) {                                        \
+    case 1001: { constexpr int SEG = 1, G = 1; __VA_ARGS__; } break;       \
+    case 2001: { constexpr int SEG = 2, G = 1; __VA_ARGS__; } break;       \
+    case 4001: { constexpr int SEG = 4, G = 1; __VA_ARGS__; } break;       \
+    case 1002: { constexpr int SEG = 1, G = 2; __VA_ARGS__; } break;       \
+    case 2002: { constexpr int SEG = 2, G = 2; __VA_ARGS__; } break;       \
+    case 4002: { constexpr int SEG = 4, G = 2; __VA_ARGS__; } break;       \
+    case 1004: { constexpr int SEG = 1, G = 4; __VA_ARGS__; } break;       \
+    case 2004: { constexpr int SEG = 2, G = 4; __VA_ARGS__; } break;       \
+    case 4004: { constexpr int SEG = 4, G = 4; __VA_ARGS__; } break;       \
+    case 2008: { constexpr int SEG = 2, G = 8; __VA_ARGS__; } break;       \
+    case 4008: { constexpr int SEG = 4, G = 8; __VA_ARGS__; } break;       \
+    case 2016: { constexpr int SEG = 2, G = 16; __VA_ARGS__; } break;      \
+    case 4016: { constexpr int SEG = 4, G = 16; __VA_ARGS__; } break;      \
+    case 4032: { constexpr int SEG = 4, G = 32; __VA_ARGS__; } break;      \
+    case 4064: { constexpr int SEG = 4, G = 64; __VA_ARGS__; } break;      \
+    default: return fail(RAMBO_EINVAL, "unsupported row split seg=%d lanes=%d", (int)(SEGV), (int)(GV)); \
+    }
+
+// Enqueue the batched form's kernels on stream s (captured into the graph).
+static int enqueue_batched(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_t *seqs, const uint64_t *offs,
+                           uint64_t n, uint64_t *out, hipStream_t s) {
+    const Index ix = make_index(h);
+    const uint32_t mw = h->R * h->RW;
+    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, offs, n, mw,
+                       (uint32_t)tu.tile, bg.bb);
+    hipLaunchKernelGGL(k_scan_u64, dim3(1), dim3(1024), 0, s, bg.bb.extra, n, bg.bb.extra_off);
+    const int G = (int)h->RW / tu.seg;
+    const uint32_t mwords = (mw + 1) & ~1u;
+    int use_res = 1;
+    size_t lds = (size_t)tu.wpb * (mwords + 2 * h->W) * 4;
+    if (lds > kMaxLds) {
+        use_res = 0;
+        lds = (size_t)tu.wpb * mwords * 4;
+    }
+    const unsigned blocks = (unsigned)std::max(1, h->n_cu * tu.waves_per_cu / tu.wpb);
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
+    RAMBO_DISPATCH_SEG_G_B(tu.seg, G,
+        hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs, n, out,
+                           bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab));
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+static int make_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
+                      uint64_t *out, std::shared_ptr<BatchGraph> &res) {
+    auto bg = std::make_shared<BatchGraph>();
+    bg->n = n;
+    const size_t mw = (size_t)h->R * h->RW;
+    const size_t bytes_mask = ((n * mw * 4) + 255) & ~(size_t)255;
+    const size_t bytes_done = ((n * 4) + 255) & ~(size_t)255;
+    const size_t bytes_extra = ((n * 8) + 255) & ~(size_t)255;
+    const size_t bytes_off = (((n + 1) * 8) + 255) & ~(size_t)255;
+    HIP_CHECK(hipMalloc(&bg->mem, bytes_mask + bytes_done + bytes_extra + bytes_off + 256));
+    char *p = (char *)bg->mem;
+    bg->bb.rmask = (uint32_t *)p; p += bytes_mask;
+    bg->bb.done = (uint32_t *)p; p += bytes_done;
+    bg->bb.extra = (uint64_t *)p; p += bytes_extra;
+    bg->bb.extra_off = (uint64_t *)p; p += bytes_off;
+    bg->bb.head = (unsigned long long *)p;
+    HIP_CHECK(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
+    int st = enqueue_batched(h, tu, *bg, seqs, offs, n, out, h->aux);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->aux, &g);
+    if (st != RAMBO_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(RAMBO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    bg->graph = g;
+    HIP_CHECK(hipGraphInstantiate(&bg->exec, g, nullptr, nullptr, 0));
+    res = bg;
+    return RAMBO_OK;
+}
+
+static std::string graph_key(const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%p/%p/%llu/%p/%d.%d.%d.%d.%d", (const void *)seqs, (const void *)offs,
+             (unsigned long long)n, (void *)out, tu.seg, tu.tile, tu.waves_per_cu, tu.wpb, tu.grab);
+    return buf;
+}
+
+static int run_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
+                     uint64_t *out, hipStream_t s) {
+    std::shared_ptr<BatchGraph> bg;
+    {
+        std::lock_guard<std::mutex> g(h->mu);
+        const std::string key = graph_key(tu, seqs, offs, n, out);
+        auto it = h->graphs.find(key);
+        if (it != h->graphs.end()) {
+            bg = it->second;
+        } else {
+            if (h->graphs.size() >= 16) h->graphs.clear();
+            int st = make_graph(h, tu, seqs, offs, n, out, bg);
+            if (st != RAMBO_OK) return st;
+            h->graphs[key] = bg;
+        }
+    }
+    HIP_CHECK(hipGraphLaunch(bg->exec, s));
+    return RAMBO_OK;
+}
+
+void drop_graphs(rambo_s *h) { h->graphs.clear(); }
+
+// ---------------------------------------------------------------------------
+// autotuner: coordinate search over the launch shape on the caller's batch
+// (every candidate computes the same bits), cached per index shape.
+// ---------------------------------------------------------------------------
+static std::string tune_key(const rambo_s *h) {
+    hipDeviceProp_t prop;
+    const char *arch = "gpu";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s K=%llu B=%u R=%u eta=%u m=%llu ee=%d", arch, (unsigned long long)h->K, h->B, h->R,
+             h->eta, (unsigned long long)h->m, h->early_exit);
+    std::string s = buf;
+    for (auto &c : s)
+        if (c == ':') c = '_';
+    return s;
+}
+
+static bool tune_cache_load(rambo_s *h) {
+    const char *path = getenv("RAMBO_TUNE_CACHE");
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line, key = tune_key(h);
+    while (std::getline(f, line)) {
+        const size_t bar = line.find('|');
+        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        Tune t;
+        if (sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.seg, &t.tile, &t.waves_per_cu, &t.wpb, &t.grab) == 5) {
+            h->tune = t;
+            return true;
+        }
+    }
+    return false;
+}
+
+static void tune_cache_store(const rambo_s *h) {
+    const char *path = getenv("RAMBO_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << tune_key(h) << "|" << h->tune.seg << " " << h->tune.tile << " " << h->tune.waves_per_cu << " "
+      << h->tune.wpb << " " << h->tune.grab << "\n";
+}
+
+static int time_candidate(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
+                          uint64_t *out, hipStream_t s, float &best_ms) {
+    hipEvent_t a, b;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&b));
+    int st = run_graph(h, tu, seqs, offs, n, out, s);  // warm-up (and graph build)
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && st == RAMBO_OK; rep++) {
+        (void)hipEventRecord(a, s);
+        st = run_graph(h, tu, seqs, offs, n, out, s);
+        (void)hipEventRecord(b, s);
+        if (hipEventSynchronize(b) != hipSuccess) st = fail(RAMBO_EDEVICE, "autotune: run failed");
+        float ms = 0;
+        if (st == RAMBO_OK) {
+            (void)hipEventElapsedTime(&ms, a, b);
+            best = std::min(best, ms);
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    best_ms = best;
+    return st;
+}
+
+static int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out, hipStream_t s) {
+    Tune best = h->tune;
+    best.seg = default_seg(h->RW);
+    float best_ms = 0;
+    int st = time_candidate(h, best, seqs, offs, n, out, s, best_ms);
+    if (st != RAMBO_OK) return st;
+    auto consider = [&](Tune t) -> int {
+        if ((int)h->RW % t.seg || (int)h->RW / t.seg > 64) return RAMBO_OK;
+        float ms = 0;
+        int st2 = time_candidate(h, t, seqs, offs, n, out, s, ms);
+        if (st2 != RAMBO_OK) return st2;
+        if (ms < best_ms * 0.98f) { best = t; best_ms = ms; }
+        return RAMBO_OK;
+    };
+    for (int tile : {64, 256, 512}) { Tune t = best; t.tile = tile; if ((st = consider(t))) return st; }
+    for (int wpc : {4, 16, 32}) { Tune t = best; t.waves_per_cu = wpc; if ((st = consider(t))) return st; }
+    for (int seg : {1, 2, 4}) { Tune t = best; t.seg = seg; if (t.seg != best.seg && (st = consider(t))) return st; }
+    for (int grab : {2, 4}) { Tune t = best; t.grab = grab; if ((st = consider(t))) return st; }
+    for (int wpb : {1, 2}) { Tune t = best; t.wpb = wpb; if (t.waves_per_cu % wpb == 0 && (st = consider(t))) return st; }
+    h->tune = best;
+    {
+        std::lock_guard<std::mutex> g(h->mu);
+        drop_graphs(h);  // keep only graphs of the chosen shape
+    }
+    return RAMBO_OK;
+}
+
+int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
+                       hipStream_t s) {
+    if (!h->tuned) {
+        h->tune.seg = default_seg(h->RW);
+        const char *mode = getenv("RAMBO_TUNE");
+        const bool off = mode && !strcmp(mode, "off");
+        if (!off && !tune_cache_load(h)) {
+            int st = autotune(h, seqs, offs, n, out, s);
+            if (st != RAMBO_OK) return st;
+            tune_cache_store(h);
+        }
+        h->tuned = true;
+    }
+    return run_graph(h, h->tune, seqs, offs, n, out, s);
+}
+
+}  // namespace rambo
+
+using namespace rambo;
+
+RAMBO_API int rambo_autotune(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n, uint64_t *out,
+                             void *stream) {
+    if (!h || !seqs || !offsets || !out || n == 0) return fail(RAMBO_EINVAL, "rambo_autotune: bad argument");
+    int st = autotune(h, seqs, offsets, n, out, (hipStream_t)stream);
+    if (st == RAMBO_OK) h->tuned = true;
+    return st;
+}
+
+RAMBO_API int rambo_get_tune(const rambo_t *h, rambo_tune_t *t) {
+    if (!h || !t) return fail(RAMBO_EINVAL, "rambo_get_tune: null argument");
+    t->seg = h->tune.seg ? h->tune.seg : default_seg(h->RW);
+    t->tile = h->tune.tile;
+    t->waves_per_cu = h->tune.waves_per_cu;
+    t->wpb = h->tune.wpb;
+    t->grab = h->tune.grab;
+    t->tuned = h->tuned ? 1 : 0;
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_set_tune(rambo_t *h, const rambo_tune_t *t) {
+    if (!h || !t) return fail(RAMBO_EINVAL, "rambo_set_tune: null argument");
+    if (!(t->seg == 1 || t->seg == 2 || t->seg == 4) || (int)h->RW % t->seg || (int)h->RW / t->seg > 64 ||
+        t->tile < 64 || t->tile % 64 || t->waves_per_cu < 1 || t->waves_per_cu > 64 ||
+        !(t->wpb == 1 || t->wpb == 2 || t->wpb == 4) || t->grab < 1 || t->grab > 64)
+        return fail(RAMBO_EINVAL, "rambo_set_tune: launch shape out of range");
+    std::lock_guard<std::mutex> g(h->mu);
+    h->tune.seg = t->seg;
+    h->tune.tile = t->tile;
+    h->tune.waves_per_cu = t->waves_per_cu;
+    h->tune.wpb = t->wpb;
+    h->tune.grab = t->grab;
+    h->tuned = true;
+    drop_graphs(h);
+    return RAMBO_OK;
+}

@@ -1,0 +1,130 @@
+// Construction (Algorithm 1): every term of document d sets, in every
+// repetition r and for every Bloom hash j, bit phi_r(d) of row
+// (r, h_{r,j}(term)) -- one atomic OR of one bit per (term, r, j). Bits are
+// only ever set, so the result is independent of order and of repeats
+// (streaming insertion, Section 3.2, is the same kernel on new documents).
+#include "rambo_int.h"
+
+namespace rambo {
+
+__device__ __forceinline__ void scatter_term(const Index &ix, uint64_t x, uint64_t d) {
+#pragma unroll
+    for (int r = 0; r < MAXR; r++) {
+        if (r < (int)ix.R) {
+            const uint32_t b = ix.phi[(uint64_t)r * ix.K + d];
+            const uint32_t bit = 1u << (b & 31);
+#pragma unroll
+            for (int j = 0; j < MAXETA; j++) {
+                if (j < (int)ix.eta) {
+                    const uint64_t pos = bloom_pos(ix, (uint32_t)r * ix.eta + j, x);
+                    atomicOr(ix.rows + (((uint64_t)r * ix.m + pos) << ix.log2RW) + (b >> 5), bit);
+                }
+            }
+        }
+    }
+}
+
+// largest k < n with off[k] <= p (off non-decreasing, off[0] <= p)
+__device__ __forceinline__ uint64_t find_doc(const uint64_t *off, uint64_t n, uint64_t p) {
+    uint64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Documents given as k-mer codes: kmers[koff[i] .. koff[i+1]) belong to doc_ids[i].
+__global__ __launch_bounds__(256) void k_build_kmers(Index ix, const uint64_t *__restrict__ kmers,
+                                                     const uint64_t *__restrict__ koff,
+                                                     const uint64_t *__restrict__ doc_ids, uint64_t n_docs,
+                                                     unsigned long long *invalid) {
+    const uint64_t first = koff[0], last = koff[n_docs];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = first + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < last; i += stride) {
+        const uint64_t k = find_doc(koff, n_docs, i);
+        const uint64_t d = doc_ids[k], x = kmers[i];
+        if (d >= ix.K || (x >> 62)) {
+            atomicAdd(invalid, 1ULL);
+            continue;
+        }
+        scatter_term(ix, canonical(x), d);
+    }
+}
+
+// Documents given as sequences: seqs[offs[i] .. offs[i+1]) is document
+// doc_ids[i]; its terms are its valid 31-windows. A wave takes 64
+// consecutive byte positions of the concatenation per step.
+__global__ __launch_bounds__(256) void k_build_seqs(Index ix, const uint8_t *__restrict__ seqs,
+                                                    const uint64_t *__restrict__ offs,
+                                                    const uint64_t *__restrict__ doc_ids, uint64_t n_docs,
+                                                    unsigned long long *invalid) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t first = offs[0], last = offs[n_docs];
+    const uint64_t nchunks = last > first ? (last - first + 63) / 64 : 0;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t ch = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; ch < nchunks; ch += nwaves) {
+        const uint64_t p0 = first + ch * 64, p = p0 + lane;
+        uint64_t k = find_doc(offs, n_docs, p0);
+        while (k + 1 < n_docs && offs[k + 1] <= p) k++;
+        const uint64_t dend = offs[k + 1];
+        const uint32_t c0 = p < last ? seqs[p] : 0u;
+        const uint32_t c1 = (lane < 30 && p + 64 < last) ? seqs[p + 64] : 0u;
+        const Window w = extract_windows(c0, c1, lane);
+        if (w.valid && p + 31 <= dend) {
+            const uint64_t d = doc_ids[k];
+            if (d >= ix.K) atomicAdd(invalid, 1ULL);
+            else scatter_term(ix, w.canon, d);
+        }
+    }
+}
+
+// BFU(r, b) as a plain m-bit filter: lane l of a wave reads row base + l.
+__global__ __launch_bounds__(256) void k_dump_bfu(Index ix, uint32_t r, uint32_t b, uint64_t *out) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t words = (ix.m + 63) / 64;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < words; w += nwaves) {
+        const uint64_t p = w * 64 + lane;
+        uint32_t bit = 0;
+        if (p < ix.m) bit = (ix.rows[(((uint64_t)r * ix.m + p) << ix.log2RW) + (b >> 5)] >> (b & 31)) & 1u;
+        const uint64_t word = __ballot(bit);
+        if (lane == 0) out[w] = word;
+    }
+}
+
+static unsigned grid_for(const rambo_s *h, uint64_t work_waves, unsigned per_cu) {
+    uint64_t cap = (uint64_t)h->n_cu * per_cu;
+    uint64_t blocks = (work_waves + 3) / 4;
+    if (blocks > cap) blocks = cap;
+    return (unsigned)(blocks ? blocks : 1);
+}
+
+int launch_build_kmers(rambo_s *h, const uint64_t *kmers, const uint64_t *koff, const uint64_t *doc_ids,
+                       uint64_t n_docs, hipStream_t s) {
+    // the grid is persistent (grid-stride); the k-mer count is only known on the device
+    const unsigned grid = (unsigned)h->n_cu * 16;
+    hipLaunchKernelGGL(k_build_kmers, dim3(grid), dim3(256), 0, s, make_index(h), kmers, koff, doc_ids, n_docs,
+                       h->d_invalid);
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+int launch_build_seqs(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, const uint64_t *doc_ids,
+                      uint64_t n_docs, hipStream_t s) {
+    const unsigned grid = (unsigned)h->n_cu * 16;
+    hipLaunchKernelGGL(k_build_seqs, dim3(grid), dim3(256), 0, s, make_index(h), seqs, offs, doc_ids, n_docs,
+                       h->d_invalid);
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+int launch_dump_bfu(rambo_s *h, uint32_t r, uint32_t b, uint64_t *d_out, hipStream_t s) {
+    const uint64_t words = (h->m + 63) / 64;
+    hipLaunchKernelGGL(k_dump_bfu, dim3(grid_for(h, words, 16)), dim3(256), 0, s, make_index(h), r, b, d_out);
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+}  // namespace rambo

@@ -1,0 +1,301 @@
+// Plain one-batch query kernels (Algorithm 2; Section 3.3.1 for sequences)
+// and the bitset -> id-list compaction.
+//
+// Per term: R * eta row reads (one per Bloom hash and repetition), ANDed
+// over j into the B-bit mask M_r of positive BFUs of repetition r. A
+// sequence ANDs the masks of its terms across the lanes of its wave and
+// stops at the first repetition whose mask is empty. The per-document AND
+// over repetitions ("resolve") runs on the masks staged in LDS.
+#include "rambo_int.h"
+
+namespace rambo {
+
+#define RAMBO_DISPATCH_SEG_G(SEGV, GV, ...)                                  \
+    switch ((SEGV) * 1000 + (GV)) {                                          \
+    case 1001: { constexpr int SEG = 1, G = 1; __VA_ARGS__; } break;         \
+    case 2001: { constexpr int SEG = 2, G = 1; __VA_ARGS__; } break;         \
+    case 4001: { constexpr int SEG = 4, G = 1; __VA_ARGS__; } break;         \
+    case 1002: { constexpr int SEG = 1, G = 2; __VA_ARGS__; } break;         \
+    case 2002: { constexpr int SEG = 2, G = 2; __VA_ARGS__; } break;         \
+    case 4002: { constexpr int SEG = 4, G = 2; __VA_ARGS__; } break;         \
+    case 1004: { constexpr int SEG = 1, G = 4; __VA_ARGS__; } break;         \
+    case 2004: { constexpr int SEG = 2, G = 4; __VA_ARGS__; } break;         \
+    case 4004: { constexpr int SEG = 4, G = 4; __VA_ARGS__; } break;         \
+    case 2008: { constexpr int SEG = 2, G = 8; __VA_ARGS__; } break;         \
+    case 4008: { constexpr int SEG = 4, G = 8; __VA_ARGS__; } break;         \
+    case 2016: { constexpr int SEG = 2, G = 16; __VA_ARGS__; } break;        \
+    case 4016: { constexpr int SEG = 4, G = 16; __VA_ARGS__; } break;        \
+    case 4032: { constexpr int SEG = 4, G = 32; __VA_ARGS__; } break;        \
+    case 4064: { constexpr int SEG = 4, G = 64; __VA_ARGS__; } break;        \
+    default: return fail(RAMBO_EINVAL, "unsupported row split seg=%d lanes=%d", (int)(SEGV), (int)(GV)); \
+    }
+
+// -------------------------------------------------------------------------
+// single k-mer queries: 64 / G terms per wave, then one resolve per term
+// -------------------------------------------------------------------------
+template <int SEG, int G>
+__global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *__restrict__ kmers, uint64_t n,
+                                                     uint64_t *__restrict__ out, unsigned long long *invalid,
+                                                     int rmode, int use_res) {
+    constexpr int KPW = 64 / G;
+    extern __shared__ uint64_t smem64[];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t mwords = ((KPW * ix.R * ix.RW) + 1) & ~1u;
+    const uint32_t per_wave = mwords + (use_res ? 2 * ix.W : 0);
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * per_wave;
+    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + mwords) : nullptr;
+
+    const uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * KPW;
+    if (base >= n) return;
+    const uint32_t g = lane / G, seg = lane % G;
+    const uint64_t q = base + g;
+
+    Seg<SEG> acc[MAXR];
+    set_ones(acc);
+    if (q < n) {
+        const uint64_t x = kmers[q];
+        if (x >> 62) {
+            if (seg == 0) atomicAdd(invalid, 1ULL);
+#pragma unroll
+            for (int r = 0; r < MAXR; r++)
+#pragma unroll
+                for (int s = 0; s < SEG; s++) acc[r].w[s] = 0;
+        } else {
+            probe_and<SEG>(ix, canonical(x), seg, acc);
+        }
+    }
+    // stage every term's masks; alive = no repetition mask is empty
+    uint64_t alive = ~0ULL;
+    const uint64_t gm = (G >= 64) ? ~0ULL : ((1ULL << G) - 1);
+#pragma unroll
+    for (int r = 0; r < MAXR; r++) {
+        if (r < (int)ix.R) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int s = 0; s < SEG; s++) {
+                M[(g * ix.R + r) * ix.RW + seg * SEG + s] = acc[r].w[s];
+                o |= acc[r].w[s];
+            }
+            const uint64_t bal = __ballot(o != 0);
+            uint64_t a = 0;
+#pragma unroll
+            for (int t = 0; t < KPW; t++) a |= (uint64_t)(((bal >> (t * G)) & gm) != 0) << t;
+            alive &= a;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int t = 0; t < KPW; t++) {
+        const uint64_t row = base + t;
+        if (row >= n) break;
+        uint64_t *o = out + row * ix.W;
+        if (!((alive >> t) & 1)) write_zeros(o, ix.W, lane);
+        else resolve(ix, M + t * ix.R * ix.RW, res, o, lane, rmode);
+    }
+}
+
+// -------------------------------------------------------------------------
+// sequence queries, plain form: one wave per read, 64 windows per step
+// -------------------------------------------------------------------------
+template <int SEG, int G>
+__global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_t *__restrict__ seqs,
+                                                          const uint64_t *__restrict__ offs, uint64_t n,
+                                                          uint64_t *__restrict__ out, QueryOpts opt, int use_res) {
+    extern __shared__ uint64_t smem64[];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t mwords = (ix.R * ix.RW + 1) & ~1u;
+    const uint32_t per_wave = mwords + (use_res ? 2 * ix.W : 0);
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * per_wave;
+    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + mwords) : nullptr;
+
+    const uint64_t read = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (read >= n) return;
+    const uint64_t beg = offs[read];
+    uint64_t end = offs[read + 1];
+    if (end < beg) end = beg;
+    const uint64_t nwin = end - beg >= 31 ? end - beg - 30 : 0;
+
+    Seg<SEG> acc[MAXR];
+    set_ones(acc);
+    uint64_t issued = 0;
+    for (uint64_t c = 0; c < nwin; c += 64) {
+        const uint64_t p = beg + c + lane;
+        const uint32_t c0 = p < end ? seqs[p] : 0u;
+        const uint32_t c1 = (lane < 30 && p + 64 < end) ? seqs[p + 64] : 0u;
+        const Window wv = extract_windows(c0, c1, lane);
+        const bool valid = wv.valid && (c + lane < nwin);
+        Seg<SEG> cm[MAXR];
+        probe_chunk<SEG, G>(ix, wv, valid, lane, cm);
+#pragma unroll
+        for (int r = 0; r < MAXR; r++)
+#pragma unroll
+            for (int s = 0; s < SEG; s++) acc[r].w[s] &= cm[r].w[s];
+        issued += __popcll(__ballot(valid));
+        if (opt.early_exit && some_rep_empty<SEG, G>(acc, ix.R)) break;
+    }
+    if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.R * ix.eta));
+    uint64_t *o = out + read * ix.W;
+    if (some_rep_empty<SEG, G>(acc, ix.R)) {
+        write_zeros(o, ix.W, lane);
+        return;
+    }
+    if (lane < (uint32_t)G) {
+#pragma unroll
+        for (int r = 0; r < MAXR; r++)
+            if (r < (int)ix.R)
+#pragma unroll
+                for (int s = 0; s < SEG; s++) M[r * ix.RW + lane * SEG + s] = acc[r].w[s];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    resolve(ix, M, res, o, lane, opt.rmode);
+}
+
+static constexpr uint32_t kMaxLds = 64 * 1024;
+
+int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *out, hipStream_t s) {
+    const Index ix = make_index(h);
+    const int seg = default_seg(h->RW), G = (int)h->RW / seg;
+    const int KPW = 64 / G, WPB = 4;
+    const uint32_t mwords = ((KPW * h->R * h->RW) + 1) & ~1u;
+    int use_res = 1;
+    size_t lds = (size_t)WPB * (mwords + 2 * h->W) * 4;
+    if (lds > kMaxLds) {
+        use_res = 0;
+        lds = (size_t)WPB * mwords * 4;
+    }
+    const uint64_t waves = (n + KPW - 1) / KPW;
+    const uint64_t blocks = (waves + WPB - 1) / WPB;
+    if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_kmers: batch too large");
+    RAMBO_DISPATCH_SEG_G(seg, G,
+        hipLaunchKernelGGL((k_query_kmers<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, kmers, n,
+                           out, h->d_invalid, h->resolve, use_res));
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
+                            hipStream_t s, int seg) {
+    const Index ix = make_index(h);
+    const int G = (int)h->RW / seg;
+    const int WPB = 4;
+    const uint32_t mwords = (h->R * h->RW + 1) & ~1u;
+    int use_res = 1;
+    size_t lds = (size_t)WPB * (mwords + 2 * h->W) * 4;
+    if (lds > kMaxLds) {
+        use_res = 0;
+        lds = (size_t)WPB * mwords * 4;
+    }
+    const uint64_t blocks = (n + WPB - 1) / WPB;
+    if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
+    RAMBO_DISPATCH_SEG_G(seg, G,
+        hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs,
+                           offs, n, out, opt, use_res));
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+// -------------------------------------------------------------------------
+// bitsets -> ascending id lists
+// -------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_count_bits(const uint64_t *__restrict__ bits, uint64_t n, uint32_t W,
+                                                    uint64_t *__restrict__ counts) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;
+    uint64_t c = 0;
+    for (uint32_t w = lane; w < W; w += 64) c += __popcll(bits[i * W + w]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane == 0) counts[i] = c;
+}
+
+// exclusive scan of counts[0..n) into off[0..n], one workgroup
+__global__ __launch_bounds__(1024) void k_scan(const uint64_t *__restrict__ counts, uint64_t n,
+                                               uint64_t *__restrict__ off) {
+    __shared__ uint64_t part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint64_t per = (n + 1023) / 1024, lo = t * per, hi = min(n, lo + per);
+    uint64_t sum = 0;
+    for (uint64_t i = lo; i < hi; i++) sum += counts[i];
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        const uint64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint64_t run = part[t] - sum;
+    for (uint64_t i = lo; i < hi; i++) {
+        off[i] = run;
+        run += counts[i];
+    }
+    if (t == 1023) off[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ bits, uint64_t n, uint32_t W,
+                                                 const uint64_t *__restrict__ off, uint32_t *__restrict__ ids) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;
+    uint64_t base = off[i];
+    for (uint32_t w0 = 0; w0 < W; w0 += 64) {
+        const uint32_t w = w0 + lane;
+        uint64_t word = w < W ? bits[i * W + w] : 0;
+        const uint32_t pc = __popcll(word);
+        uint32_t incl = pc;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(incl, d);
+            if ((int)lane >= d) incl += v;
+        }
+        uint64_t pos = base + incl - pc;
+        while (word) {
+            const uint32_t b = (uint32_t)__builtin_ctzll(word);
+            word &= word - 1;
+            ids[pos++] = w * 64 + b;
+        }
+        base += __shfl(incl, 63);
+    }
+}
+
+int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off, uint64_t ids_cap,
+               hipStream_t s) {
+    const uint32_t W = (uint32_t)h->W;
+    uint64_t total = 0;
+    if (n == 0) {
+        HIP_CHECK(hipMemsetAsync(id_off, 0, 8, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        return RAMBO_OK;
+    }
+    uint64_t *counts = nullptr;
+    HIP_CHECK(hipMallocAsync((void **)&counts, n * 8, s));
+    const unsigned blocks = (unsigned)((n + 3) / 4);
+    hipLaunchKernelGGL(k_count_bits, dim3(blocks), dim3(256), 0, s, bits, n, W, counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, n, id_off);
+    hipError_t e = hipMemcpyAsync(&total, id_off + n, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(counts, s);
+        return fail(RAMBO_EDEVICE, "rambo_query_seqs_ids: %s", hipGetErrorString(e));
+    }
+    if (total > ids_cap) {
+        (void)hipFreeAsync(counts, s);
+        return fail(RAMBO_ETRUNC, "rambo_query_seqs_ids: %llu ids do not fit %llu", (unsigned long long)total,
+                    (unsigned long long)ids_cap);
+    }
+    if (total > 0) {
+        if (!ids) {
+            (void)hipFreeAsync(counts, s);
+            return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null ids");
+        }
+        hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, bits, n, W, id_off, ids);
+    }
+    HIP_CHECK(hipFreeAsync(counts, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return RAMBO_OK;
+}
+
+}  // namespace rambo

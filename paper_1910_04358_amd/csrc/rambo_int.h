@@ -1,0 +1,114 @@
+// Host-side internals of librambo: the handle, error reporting and the
+// launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rambo.h"
+#include "rambo_dev.h"
+
+#define RAMBO_API extern "C" __attribute__((visibility("default")))
+
+namespace rambo {
+
+int fail(int status, const char *fmt, ...);  // records the message, returns status
+int ok();                                     // clears nothing, returns RAMBO_OK
+
+#define HIP_CHECK(expr)                                                                           \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return ::rambo::fail(RAMBO_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+// Launch shape of the sequence-query kernels; what the autotuner searches.
+struct Tune {
+    int seg = 4;          // 32-bit words of a row one lane reads (1, 2 or 4)
+    int tile = 128;       // windows per work item (multiple of 64), batched form
+    int waves_per_cu = 8; // resident waves per CU of the persistent grid
+    int wpb = 4;          // waves per workgroup
+    int grab = 1;         // work items taken per queue access
+};
+
+struct BatchGraph;  // batched-form state for one set of buffers (batch.hip)
+
+}  // namespace rambo
+
+struct rambo_s {
+    uint64_t K = 0, m = 0, seed = 0, W = 0;
+    uint32_t B = 0, R = 0, eta = 0, RW = 0, log2RW = 0;
+    int device = 0, n_cu = 0;
+    uint64_t rows_bytes = 0;
+    uint32_t *rows = nullptr;
+    rambo::HashParams *d_hp = nullptr;
+    uint16_t *d_phi = nullptr;
+    uint32_t *d_boff = nullptr, *d_bdoc = nullptr;
+    unsigned long long *d_invalid = nullptr;
+    std::vector<uint64_t> pa, pb, Alo, Ahi, Clo, Chi;
+    std::vector<uint32_t> phi;  // [R][K]
+    int mode = RAMBO_MODE_PLAIN, resolve = RAMBO_RESOLVE_AUTO, early_exit = 1;
+    unsigned long long *probe_counter = nullptr;
+    bool tuned = false;
+    rambo::Tune tune;
+    hipStream_t aux = nullptr;  // internal stream (graph capture, sync helpers)
+    std::mutex mu;              // guards the graph cache and tuner
+    std::map<std::string, std::shared_ptr<rambo::BatchGraph>> graphs;
+};
+
+namespace rambo {
+
+inline Index make_index(const rambo_s *h) {
+    Index ix;
+    ix.rows = h->rows;
+    ix.hp = h->d_hp;
+    ix.phi = h->d_phi;
+    ix.boff = h->d_boff;
+    ix.bdoc = h->d_bdoc;
+    ix.m = h->m;
+    ix.K = h->K;
+    ix.B = h->B;
+    ix.R = h->R;
+    ix.eta = h->eta;
+    ix.RW = h->RW;
+    ix.log2RW = h->log2RW;
+    ix.W = (uint32_t)h->W;
+    return ix;
+}
+
+struct QueryOpts {
+    int rmode;                    // RAMBO_RESOLVE_*
+    int early_exit;
+    unsigned long long *probes;   // may be null
+};
+
+// build.hip
+int launch_build_kmers(rambo_s *h, const uint64_t *kmers, const uint64_t *koff, const uint64_t *doc_ids,
+                       uint64_t n_docs, hipStream_t s);
+int launch_build_seqs(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, const uint64_t *doc_ids,
+                      uint64_t n_docs, hipStream_t s);
+int launch_dump_bfu(rambo_s *h, uint32_t r, uint32_t b, uint64_t *d_out, hipStream_t s);
+
+// query.hip
+int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *out, hipStream_t s);
+int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
+                            uint64_t *out, hipStream_t s, int seg);
+int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off,
+               uint64_t ids_cap, hipStream_t s);
+
+// batch.hip
+int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
+                       hipStream_t s);
+void drop_graphs(rambo_s *h);
+
+// largest power-of-two segment (<= 4 words) that divides a row
+inline int default_seg(uint32_t RW) { return RW >= 4 ? 4 : (int)RW; }
+
+}  // namespace rambo

@@ -1,0 +1,230 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle,
+on the same seeded inputs, at sizes the oracle finishes in seconds that still
+span many tiles and ragged tails: the whole index, every query result, every
+execution form and resolve strategy, and the edge cases."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from paper_1910_04358_amd import rambo as rb
+from tests import _ref
+from tests.gpu_util import build_gpu_seqs, build_oracle, make_reads, reads_to_dev, to_dev, to_host_u64
+
+pytestmark = pytest.mark.gpu
+
+# (name, K, B, R, m, eta, doc model, read model, n_reads)
+CASES = {
+    # row of 1 word (B <= 32), eta = 3 as the K=1000 workload
+    "rw1": (600, 32, 4, 1 << 22, 3,
+            gen.DocModel(seed=71, n_docs=600, length=20_000, docs_per_anc=50, mu_lo=0.01, mu_hi=0.01),
+            gen.ReadModel(qseed=81, src_lo=0, src_hi=600, len_kind=0, median=300, sigma=1.0, lo=31, hi=5000,
+                          err_lo=0.0, err_hi=0.01), 3000),
+    # row of 4 words (B = 100), the K=10,000 workload's shape
+    "rw4": (1000, 100, 5, 1 << 22, 2,
+            gen.DocModel(seed=72, n_docs=1000, length=20_000, docs_per_anc=100, mu_lo=0.005, mu_hi=0.02),
+            gen.ReadModel(qseed=82, src_lo=0, src_hi=1000, len_kind=0, median=300, sigma=1.0, lo=31, hi=10_000,
+                          err_lo=0.0, err_hi=0.01), 3000),
+    # row of 32 words split over 8 lanes (B = 1000), the K=101,000 workload's shape
+    "rw32": (2000, 1000, 6, 1 << 21, 2,
+             gen.DocModel(seed=73, n_docs=2000, length=10_000, docs_per_anc=100, mu_lo=0.01, mu_hi=0.01),
+             gen.ReadModel(qseed=83, src_lo=0, src_hi=2000, len_kind=1, lo=100, hi=1000, err_lo=0.01,
+                           err_hi=0.01), 2000),
+}
+
+_built = {}
+
+
+def setup_case(name):
+    if name in _built:
+        return _built[name]
+    K, B, R, m, eta, dm, rm, nr = CASES[name]
+    seed = 5000 + len(_built)
+    idx = rb.Rambo(K, B, R, m, eta, seed)
+    build_gpu_seqs(idx, dm, 0, dm.n_docs)
+    o = build_oracle((K, B, R, m, eta, seed), dm)
+    reads = gen.reads(dm, rm, nr)
+    want, _ = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2, early_exit=True)
+    _built[name] = (idx, o, dm, reads, want)
+    return _built[name]
+
+
+def test_hash_parameters_and_cells_match_the_definition():
+    idx = rb.Rambo(1000, 100, 5, 1 << 22, 2, 4242)
+    o = oracle.Oracle(1000, 100, 5, 1 << 22, 2, 4242, alloc_bits=False)
+    p, q = idx.hash_params(), o.params()
+    for k in p:
+        assert np.array_equal(p[k], q[k]), k
+    assert np.array_equal(idx.phi_table().astype(np.int64), o.phis())
+    idx.close()
+
+
+def test_c1_index_and_kmer_queries_bit_exact():
+    """Workload 1 in full: 100 i.i.d. documents of 20,000 bp, R=3, B=10,
+    m=2^20, eta=2; 10,000 single k-mer queries (half present)."""
+    w = gen.workload(1)
+    o = build_oracle((w.K, w.B, w.R, w.m, w.eta, w.index_seed), w.docs)
+    # the same documents given as host k-mer codes, half of them reverse complemented
+    idx = rb.Rambo(w.K, w.B, w.R, w.m, w.eta, w.index_seed)
+    for d in range(w.K):
+        codes = w.docs.window_codes(d)
+        idx.insert(d, _ref.revcomp_np(codes) if d % 2 else codes)
+    assert np.array_equal(idx.bfu_major(), o.bits())
+    # and as sequences (device extraction)
+    idx2 = rb.Rambo(w.K, w.B, w.R, w.m, w.eta, w.index_seed)
+    build_gpu_seqs(idx2, w.docs, 0, w.K, chunk=37)
+    assert np.array_equal(idx2.bfu_major(), o.bits())
+    q, src = gen.kmer_queries(w.docs, w.kmer_qseed, w.n_kmer_queries, 0.5)
+    want = o.query_kmers(q)
+    for resolve in (rb.RESOLVE_AUTO, rb.RESOLVE_DENSE, rb.RESOLVE_CANDIDATE):
+        idx.set_resolve(resolve)
+        got = to_host_u64(idx.query_kmers(to_dev(q)))
+        assert np.array_equal(got, want), resolve
+    # reverse-complemented queries give the same answers
+    got = to_host_u64(idx.query_kmers(to_dev(_ref.revcomp_np(q))))
+    assert np.array_equal(got, want)
+    idx.close()
+    idx2.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_index_bits_match_oracle(name):
+    idx, o, dm, reads, want = setup_case(name)
+    bits = o.bits()
+    rng = np.random.default_rng(1)
+    pairs = [(r, b) for r in range(idx.R) for b in range(idx.B)]
+    if len(pairs) > 120:
+        pairs = [pairs[i] for i in rng.choice(len(pairs), 120, replace=False)]
+    for r, b in pairs:
+        assert np.array_equal(idx.dump_bfu(r, b), bits[r, b]), (r, b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_read_queries_every_form_bit_exact(name):
+    idx, o, dm, reads, want = setup_case(name)
+    seqs, offs = reads_to_dev(reads)
+    assert (want.any(axis=1)).sum() > 20  # the batch has non-empty answers
+    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+        idx.set_mode(mode)
+        for resolve in (rb.RESOLVE_AUTO, rb.RESOLVE_DENSE, rb.RESOLVE_CANDIDATE):
+            idx.set_resolve(resolve)
+            for ee in (True, False):
+                idx.set_early_exit(ee)
+                got = to_host_u64(idx.query_seqs(seqs, offs))
+                bad = np.nonzero((got != want).any(axis=1))[0]
+                assert bad.size == 0, (name, mode, resolve, ee, bad[:5])
+    idx.set_early_exit(True)
+    idx.set_resolve(rb.RESOLVE_AUTO)
+    idx.set_mode(rb.MODE_PLAIN)
+
+
+@pytest.mark.parametrize("name", ["rw4", "rw32"])
+def test_batched_launch_shapes_agree(name):
+    """Every launch shape the autotuner may pick computes the same bits."""
+    idx, o, dm, reads, want = setup_case(name)
+    seqs, offs = reads_to_dev(reads)
+    idx.set_mode(rb.MODE_BATCHED)
+    segs = [s for s in (1, 2, 4) if idx.row_words % s == 0 and idx.row_words // s <= 64]
+    for seg in segs:
+        for tile, wpc, wpb, grab in ((64, 4, 1, 1), (128, 8, 4, 2), (512, 32, 2, 4)):
+            idx.set_tune(rb.Tune(seg, tile, wpc, wpb, grab))
+            got = to_host_u64(idx.query_seqs(seqs, offs))
+            assert np.array_equal(got, want), (seg, tile, wpc, wpb, grab)
+    idx.set_mode(rb.MODE_PLAIN)
+
+
+def test_zero_false_negatives_and_strand_invariance():
+    idx, o, dm, reads, want = setup_case("rw4")
+    got = to_host_u64(idx.query_seqs(*reads_to_dev(reads)))
+    clean = np.nonzero((reads.src >= 0) & (reads.nerr == 0))[0]
+    assert clean.size > 100
+    for i in clean:
+        d = int(reads.src[i])
+        assert (got[i, d >> 6] >> np.uint64(d & 63)) & np.uint64(1), i
+    rc = [_ref.revcomp_seq(reads.read(i)) for i in range(reads.n)]
+    s2, o2 = make_reads(rc)
+    got_rc = to_host_u64(idx.query_seqs(to_dev(s2), to_dev(o2)))
+    assert np.array_equal(got_rc, got)
+
+
+def test_edge_case_reads():
+    """Empty, shorter than k, exactly k, all-invalid, invalid bytes inside,
+    lowercase, and a 10,000 bp read spanning many tiles."""
+    idx, o, dm, reads, want = setup_case("rw4")
+    d5 = dm.doc(5)
+    cases = [b"", b"A", b"ACGT" * 7 + b"AC", d5[100:131], b"N" * 200, d5[0:200] + b"N" + d5[201:400],
+             d5[1000:1300].lower(), d5[:10_000], b"ACGTX" * 40, d5[3000:3031] + b"\x00" + d5[3031:3100],
+             d5[5000:5100]]
+    seqs, offs = make_reads(cases)
+    wantc = np.stack([o.query_seq(s) for s in cases])
+    everyone = _ref.ids_to_bits(range(idx.K), idx.K)
+    for i in (0, 1, 2, 4, 8):
+        assert np.array_equal(wantc[i], everyone)
+    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+        idx.set_mode(mode)
+        idx.set_tune(rb.Tune(4, 64, 8, 4, 1))
+        got = to_host_u64(idx.query_seqs(to_dev(seqs), to_dev(offs)))
+        assert np.array_equal(got, wantc), mode
+    idx.set_mode(rb.MODE_PLAIN)
+
+
+def test_invalid_kmer_values_reported():
+    idx, o, dm, reads, want = setup_case("rw1")
+    q = np.array([5, 1 << 62, 7, (1 << 64) - 1], dtype=np.uint64)
+    got = to_host_u64(idx.query_kmers(to_dev(q)))
+    assert not got[1].any() and not got[3].any()
+    with pytest.raises(rb.RamboError) as e:
+        idx.sync()
+    assert e.value.status == rb.EINVAL
+    idx.sync()  # the count was consumed
+    with pytest.raises(rb.RamboError):
+        idx.insert(0, np.array([1 << 62], dtype=np.uint64))
+    with pytest.raises(rb.RamboError):
+        idx.insert(idx.K, np.array([1], dtype=np.uint64))
+
+
+def test_id_lists_match_bitsets():
+    idx, o, dm, reads, want = setup_case("rw32")
+    seqs, offs = reads_to_dev(reads)
+    ids, id_off = idx.query_seqs_ids(seqs, offs, ids_cap=10_000_000)
+    ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
+    for i in range(reads.n):
+        assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(want[i], idx.K))
+    with pytest.raises(rb.RamboError) as e:
+        idx.query_seqs_ids(seqs, offs, ids_cap=0)
+    assert e.value.status == rb.ETRUNC and e.value.required == int(id_off[-1])
+
+
+def test_build_is_deterministic_and_order_free():
+    K, B, R, m, eta, dm, rm, nr = CASES["rw4"]
+    a = rb.Rambo(K, B, R, m, eta, 99)
+    build_gpu_seqs(a, dm, 0, K, chunk=1000)
+    b = rb.Rambo(K, B, R, m, eta, 99)
+    order = np.random.default_rng(3).permutation(K)
+    docs = dm.docs(0, K).reshape(K, -1)[order].reshape(-1)
+    offs = np.arange(K + 1, dtype=np.uint64) * np.uint64(dm.length)
+    b.insert_seqs(to_dev(order.astype(np.uint64)), to_dev(docs), to_dev(offs))
+    b.sync()
+    assert np.array_equal(a.copy_rows(), b.copy_rows())
+    # streaming: the first half, then the second half, equals all at once
+    c = rb.Rambo(K, B, R, m, eta, 99)
+    build_gpu_seqs(c, dm, 0, K // 2)
+    build_gpu_seqs(c, dm, K // 2, K - K // 2)
+    assert np.array_equal(a.copy_rows(), c.copy_rows())
+    for x in (a, b, c):
+        x.close()
+
+
+def test_insert_batch_kmers_equals_sequences():
+    K, B, R, m, eta, dm, rm, nr = CASES["rw32"]
+    a = rb.Rambo(K, B, R, m, eta, 7)
+    build_gpu_seqs(a, dm, 0, 300)
+    b = rb.Rambo(K, B, R, m, eta, 7)
+    codes = [dm.window_codes(d) for d in range(300)]
+    koff = np.zeros(301, dtype=np.uint64)
+    koff[1:] = np.cumsum([c.size for c in codes])
+    b.insert_batch(to_dev(np.arange(300, dtype=np.uint64)), to_dev(koff), to_dev(np.concatenate(codes)))
+    b.sync()
+    assert np.array_equal(a.copy_rows(), b.copy_rows())
+    a.close()
+    b.close()
