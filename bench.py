@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the RAMBO hot path on one MI355X.
+
+Workload (the K = 10,000 configuration the headline metric is quoted on):
+K = 10,000 documents (100 random ancestors x 100 mutants of 500 kbp, per
+document substitution rate uniform in 0.5-2 %), R = 5, B = 100, m = 2^29
+bits per BFU, eta = 2 (a 40 GiB bit-sliced index); 100,000 reads with
+log-normal lengths (median 300 bp, sigma 1, clipped to 31-10,000 bp), 70 %
+copied from a random document with 0-1 % errors, 30 % random. Seeded,
+synthetic (the paper's ENA archive is not available).
+
+A step is one query batch of all 100,000 reads (every k-mer of every read
+counted, including those early exit skips), with the index and the reads
+resident in HBM. The batched form (persistent launch replayed from a HIP
+graph, autotuned shape) gives `value`; the plain one-launch kernel and the
+build are reported beside it, with the served form's latency when run.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+GRANULE = 64            # bytes one isolated random row read costs at the memory
+
+
+def log(*a):
+    print("[bench %7.1fs]" % (time.time() - T0), *a, file=sys.stderr, flush=True)
+
+
+T0 = time.time()
+
+
+def up(a, dev):
+    import torch
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a.view(np.int64) if a.dtype == np.uint64 else a).to(dev)
+
+
+def build_index(w, dev, docs_per_chunk=1000):
+    """Create the index, stage all documents in HBM, build in one launch."""
+    import torch
+    import gen
+    from paper_1910_04358_amd import Rambo
+
+    idx = Rambo(w.K, w.B, w.R, w.m, w.eta, w.index_seed)
+    L, nd = w.docs.length, w.docs.n_docs
+    seqs = torch.empty(nd * L, dtype=torch.uint8, device=dev)
+    host = torch.empty(docs_per_chunk * L, dtype=torch.uint8, pin_memory=True)
+    hnp = host.numpy()
+    for c0 in range(0, nd, docs_per_chunk):
+        c1 = min(nd, c0 + docs_per_chunk)
+        w.docs.docs(c0, c1 - c0, out=hnp[: (c1 - c0) * L])
+        seqs[c0 * L: c1 * L].copy_(host[: (c1 - c0) * L], non_blocking=False)
+    log("documents staged in HBM: %.2f GB" % (nd * L / 1e9))
+    offs = up(np.arange(nd + 1, dtype=np.uint64) * np.uint64(L), dev)
+    ids = up(np.arange(nd, dtype=np.uint64), dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    idx.insert_seqs(ids, seqs, offs)
+    e1.record()
+    idx.sync()
+    build_ms = e0.elapsed_time(e1)
+    kmers = nd * (L - 30)
+    del seqs
+    torch.cuda.empty_cache()
+    return idx, build_ms, kmers
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(w, sample_reads, sample_docs, nthreads):
+    """The oracle (Algorithm 2, early exit) on a bounded sample of the same
+    workload: an index of the same shape (R, B, m, eta) holding documents
+    0..sample_docs-1, queried with reads drawn from those documents with the
+    workload's length, error and random-read mix."""
+    import gen
+    import oracle
+    from dataclasses import replace
+
+    o = oracle.Oracle(w.K, w.B, w.R, w.m, w.eta, w.index_seed)
+    t = time.time()
+    step = 250
+    for c0 in range(0, sample_docs, step):
+        c1 = min(sample_docs, c0 + step)
+        o.build_docs(w.docs.docs(c0, c1 - c0), w.docs.length, c0, c1 - c0, nthreads=nthreads)
+    build_s = time.time() - t
+    log("cpu oracle: built %d documents in %.1fs" % (sample_docs, build_s))
+    rm = replace(w.reads, src_lo=0, src_hi=sample_docs, qseed=w.reads.qseed + 100)
+    reads = gen.reads(w.docs, rm, sample_reads)
+    t = time.time()
+    res, tests = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2, early_exit=True, nthreads=nthreads)
+    q_s = time.time() - t
+    kmers = reads.n_windows()
+    del o
+    return {"value": kmers / q_s, "unit": "k-mer queries/s", "cores": nthreads, "kind": "oracle",
+            "sample": "Algorithm 2 with early exit on %d reads (%d k-mers) drawn from documents 0..%d of the "
+                      "workload (same length, error and random mix), against an oracle index of the "
+                      "workload's shape (R=%d, B=%d, m=2^%d, eta=%d) holding those %d documents; "
+                      "query time %.2fs on %d threads (index build %.1fs not counted)"
+                      % (sample_reads, kmers, sample_docs - 1, w.R, w.B, int(np.log2(w.m)), w.eta,
+                         sample_docs, q_s, nthreads, build_s),
+            "reads_per_s": sample_reads / q_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) runs")
+    ap.add_argument("--cpu-reads", type=int, default=6000)
+    ap.add_argument("--cpu-docs", type=int, default=1000)
+    ap.add_argument("--only", choices=["plain", "batched"], default=None,
+                    help="time only one form (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (documents would be "
+              "sharded across GPUs with no exchange at build time; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gen
+    from paper_1910_04358_amd import MODE_BATCHED, MODE_PLAIN
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = gen.workload(3)
+    log("workload", w.name)
+    idx, build_ms, build_kmers = build_index(w, dev)
+    log("build: %.1f ms for %d k-mers" % (build_ms, build_kmers))
+
+    reads = gen.reads(w.docs, w.reads, w.n_reads)
+    n_kmers = reads.n_windows()
+    seqs, offs = up(reads.seqs, dev), up(reads.offsets, dev)
+    out = torch.empty((reads.n, idx.W), dtype=torch.int64, device=dev)
+    log("reads: %d, %d k-mers, %.1f MB" % (reads.n, n_kmers, reads.seqs.size / 1e6))
+
+    def step():
+        idx.query_seqs(seqs, offs, out=out, check=False)
+
+    result = {}
+    probes = torch.zeros(1, dtype=torch.int64, device=dev)
+    if args.only != "batched":
+        idx.set_mode(MODE_PLAIN)
+        plain_ms = time_steps(step, args.steps, args.warmup)
+        ref = out.clone()
+        idx.set_probe_counter(probes)
+        step()
+        torch.cuda.synchronize()
+        plain_probes = int(probes.item())
+        idx.set_probe_counter(None)
+        log("plain: %.3f ms/step, %.3g k-mer/s, %d probes" % (plain_ms, n_kmers / plain_ms * 1e3, plain_probes))
+        result["plain"] = {"ms_per_step": plain_ms, "kmer_per_s": n_kmers / plain_ms * 1e3,
+                           "reads_per_s": reads.n / plain_ms * 1e3, "probes": plain_probes}
+    idx.set_mode(MODE_BATCHED)
+    t = time.time()
+    step()  # autotunes the launch shape on this batch
+    torch.cuda.synchronize()
+    tune = idx.get_tune()
+    log("autotune: %.1fs -> %s" % (time.time() - t, tune))
+    if args.only != "plain":
+        batched_ms = time_steps(step, args.steps, args.warmup)
+        if args.only is None and not torch.equal(out, ref):
+            raise SystemExit("batched results differ from the plain kernel")
+        # dominant kernel: per-launch device time from events inside the graph,
+        # and the probes it issued, over the same number of launches
+        idx.set_probe_counter(probes)
+        probes.zero_()
+        kern, graph = [], []
+        for _ in range(args.steps):
+            step()
+            g_ms, k_ms = idx.last_batch_ms()
+            graph.append(g_ms)
+            kern.append(k_ms)
+        torch.cuda.synchronize()
+        issued = int(probes.item()) / args.steps
+        idx.set_probe_counter(None)
+        kern_ms = float(np.mean(kern))
+        log("batched: %.3f ms/step (graph %.3f, kernel %.3f), %.3g k-mer/s, %.0f probes/launch"
+            % (batched_ms, np.mean(graph), kern_ms, n_kmers / batched_ms * 1e3, issued))
+    else:
+        batched_ms = kern_ms = issued = float("nan")
+
+    row_bytes = idx.row_words * 4
+    io_bytes = reads.seqs.size + 8 * (reads.n + 1) + reads.n * idx.W * 8
+    alg_bytes = issued * max(GRANULE, row_bytes) + io_bytes
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    value = n_kmers / batched_ms * 1e3
+
+    cpu = None
+    if not args.no_cpu:
+        nthr = max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(w, args.cpu_reads, args.cpu_docs, nthr)
+        log("cpu oracle: %.3g k-mer/s on %d threads" % (cpu["value"], nthr))
+
+    served = None
+    if not args.no_serve:
+        try:
+            import serve_bench
+            served = serve_bench.run(idx, w, dev, log)
+        except ImportError:
+            served = None
+
+    line = {
+        "metric": "k-mer queries/s (batched form, K=10,000 documents) with read p50/p99 latency served vs plain",
+        "value": value,
+        "unit": "k-mer queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": batched_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 bitwise (u64 k-mer codes)",
+        "data": "synthetic (seeded genomes: 100 ancestors x 100 mutants of 500 kbp; 100,000 reads)",
+        "config": {"workload": w.name, "K": w.K, "B": w.B, "R": w.R, "m": w.m, "eta": w.eta,
+                   "reads": reads.n, "kmers_per_step": n_kmers, "index_bytes": idx.index_bytes,
+                   "tune": tune.__dict__},
+        "reads_per_s": reads.n / batched_ms * 1e3,
+        "build": {"ms": build_ms, "kmers": build_kmers,
+                  "input_GBps_u64_kmers": build_kmers * 8 / build_ms / 1e6,
+                  "bases_per_s": w.docs.n_docs * w.docs.length / build_ms * 1e3},
+        "plain": result.get("plain"),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_batch_main", "kernel_ms": kern_ms, "probes_per_launch": issued,
+                     "bytes_per_probe": max(GRANULE, row_bytes), "io_bytes": io_bytes},
+        "cpu_baseline": cpu,
+        "served": served,
+    }
+    print(json.dumps(line), flush=True)
+    idx.close()
+
+
+if __name__ == "__main__":
+    main()

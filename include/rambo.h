@@ -230,6 +230,13 @@ typedef struct {
 int rambo_autotune(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n, uint64_t *out,
                    void *stream);
 int rambo_get_tune(const rambo_t *h, rambo_tune_t *out);
+
+/* Device time of the most recent batched launch on this handle, from HIP
+ * events recorded inside its graph: the whole graph (graph_ms) and its
+ * persistent query kernel alone (kernel_ms). Waits for that launch.
+ * RAMBO_EINVAL if no batched launch has run or the runtime could not record
+ * events inside the graph. */
+int rambo_last_batch_ms(rambo_t *h, float *graph_ms, float *kernel_ms);
 int rambo_set_tune(rambo_t *h, const rambo_tune_t *t);
 
 #ifdef __cplusplus

@@ -35,7 +35,12 @@ struct BatchGraph {
     void *mem = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // timing events recorded inside the graph: start, before and after the
+    // persistent kernel (null if the runtime cannot capture event records)
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     ~BatchGraph() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (mem) (void)hipFree(mem);
@@ -208,31 +213,13 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
 
 static constexpr uint32_t kMaxLds = 64 * 1024;
 
-#define RAMBO_DISPATCH_SEG_G_B(SEGV, GV, ...)                              \
-    switch ((SEGV) * 1000 + (GV)) {                                        \
-    case 1001: { constexpr int SEG = 1, G = 1; __VA_ARGS__; } break;       \
-    case 2001: { constexpr int SEG = 2, G = 1; __VA_ARGS__; } break;       \
-    case 4001: { constexpr int SEG = 4, G = 1; __VA_ARGS__; } break;       \
-    case 1002: { constexpr int SEG = 1, G = 2; __VA_ARGS__; } break;       \
-    case 2002: { constexpr int SEG = 2, G = 2; __VA_ARGS__; } break;       \
-    case 4002: { constexpr int SEG = 4, G = 2; __VA_ARGS__; } break;       \
-    case 1004: { constexpr int SEG = 1, G = 4; __VA_ARGS__; } break;       \
-    case 2004: { constexpr int SEG = 2, G = 4; __VA_ARGS__; } break;       \
-    case 4004: { constexpr int SEG = 4, G = 4; __VA_ARGS__; } break;       \
-    case 2008: { constexpr int SEG = 2, G = 8; __VA_ARGS__; } break;       \
-    case 4008: { constexpr int SEG = 4, G = 8; __VA_ARGS__; } break;       \
-    case 2016: { constexpr int SEG = 2, G = 16; __VA_ARGS__; } break;      \
-    case 4016: { constexpr int SEG = 4, G = 16; __VA_ARGS__; } break;      \
-    case 4032: { constexpr int SEG = 4, G = 32; __VA_ARGS__; } break;      \
-    case 4064: { constexpr int SEG = 4, G = 64; __VA_ARGS__; } break;      \
-    default: return fail(RAMBO_EINVAL, "unsupported row split seg=%d lanes=%d", (int)(SEGV), (int)(GV)); \
-    }
 
 // Enqueue the batched form's kernels on stream s (captured into the graph).
 static int enqueue_batched(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_t *seqs, const uint64_t *offs,
                            uint64_t n, uint64_t *out, hipStream_t s) {
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
+    if (bg.ev[0]) HIP_CHECK(hipEventRecord(bg.ev[0], s));
     hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, offs, n, mw,
                        (uint32_t)tu.tile, bg.bb);
     hipLaunchKernelGGL(k_scan_u64, dim3(1), dim3(1024), 0, s, bg.bb.extra, n, bg.bb.extra_off);
@@ -246,10 +233,14 @@ static int enqueue_batched(rambo_s *h, const Tune &tu, BatchGraph &bg, const uin
     }
     const unsigned blocks = (unsigned)std::max(1, h->n_cu * tu.waves_per_cu / tu.wpb);
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
-    RAMBO_DISPATCH_SEG_G_B(tu.seg, G,
-        hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs, n, out,
-                           bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab));
+    if (bg.ev[1]) HIP_CHECK(hipEventRecord(bg.ev[1], s));
+#define RAMBO_SPLIT_BODY_                                                                                  \
+    hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs, n, out,       \
+                       bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab)
+    RAMBO_DISPATCH_SPLIT(tu.seg, G)
+#undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());
+    if (bg.ev[2]) HIP_CHECK(hipEventRecord(bg.ev[2], s));
     return RAMBO_OK;
 }
 
@@ -269,14 +260,26 @@ static int make_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uin
     bg->bb.extra = (uint64_t *)p; p += bytes_extra;
     bg->bb.extra_off = (uint64_t *)p; p += bytes_off;
     bg->bb.head = (unsigned long long *)p;
-    HIP_CHECK(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
-    int st = enqueue_batched(h, tu, *bg, seqs, offs, n, out, h->aux);
+    for (auto &ev : bg->ev) HIP_CHECK(hipEventCreate(&ev));
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(h->aux, &g);
-    if (st != RAMBO_OK) {
+    int st = RAMBO_OK;
+    hipError_t e = hipSuccess;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        HIP_CHECK(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
+        st = enqueue_batched(h, tu, *bg, seqs, offs, n, out, h->aux);
+        g = nullptr;
+        e = hipStreamEndCapture(h->aux, &g);
+        if (st == RAMBO_OK && e == hipSuccess) break;
         if (g) (void)hipGraphDestroy(g);
-        return st;
+        g = nullptr;
+        (void)hipGetLastError();
+        // retry without the timing events
+        for (auto &ev : bg->ev) {
+            if (ev) (void)hipEventDestroy(ev);
+            ev = nullptr;
+        }
     }
+    if (st != RAMBO_OK) return st;
     if (e != hipSuccess) return fail(RAMBO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
     bg->graph = g;
     HIP_CHECK(hipGraphInstantiate(&bg->exec, g, nullptr, nullptr, 0));
@@ -308,10 +311,17 @@ static int run_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint
         }
     }
     HIP_CHECK(hipGraphLaunch(bg->exec, s));
+    {
+        std::lock_guard<std::mutex> g(h->mu);
+        h->last_graph = bg;
+    }
     return RAMBO_OK;
 }
 
-void drop_graphs(rambo_s *h) { h->graphs.clear(); }
+void drop_graphs(rambo_s *h) {
+    h->graphs.clear();
+    h->last_graph.reset();
+}
 
 // ---------------------------------------------------------------------------
 // autotuner: coordinate search over the launch shape on the caller's batch
@@ -386,7 +396,7 @@ static int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint6
     int st = time_candidate(h, best, seqs, offs, n, out, s, best_ms);
     if (st != RAMBO_OK) return st;
     auto consider = [&](Tune t) -> int {
-        if ((int)h->RW % t.seg || (int)h->RW / t.seg > 64) return RAMBO_OK;
+        if ((int)h->RW % t.seg || !split_supported(t.seg, (int)h->RW / t.seg)) return RAMBO_OK;
         float ms = 0;
         int st2 = time_candidate(h, t, seqs, offs, n, out, s, ms);
         if (st2 != RAMBO_OK) return st2;
@@ -434,6 +444,20 @@ RAMBO_API int rambo_autotune(rambo_t *h, const uint8_t *seqs, const uint64_t *of
     return st;
 }
 
+RAMBO_API int rambo_last_batch_ms(rambo_t *h, float *graph_ms, float *kernel_ms) {
+    if (!h || !graph_ms || !kernel_ms) return fail(RAMBO_EINVAL, "rambo_last_batch_ms: null argument");
+    std::shared_ptr<BatchGraph> bg;
+    {
+        std::lock_guard<std::mutex> g(h->mu);
+        bg = h->last_graph;
+    }
+    if (!bg || !bg->ev[0]) return fail(RAMBO_EINVAL, "rambo_last_batch_ms: no timed batched launch");
+    HIP_CHECK(hipEventSynchronize(bg->ev[2]));
+    HIP_CHECK(hipEventElapsedTime(graph_ms, bg->ev[0], bg->ev[2]));
+    HIP_CHECK(hipEventElapsedTime(kernel_ms, bg->ev[1], bg->ev[2]));
+    return RAMBO_OK;
+}
+
 RAMBO_API int rambo_get_tune(const rambo_t *h, rambo_tune_t *t) {
     if (!h || !t) return fail(RAMBO_EINVAL, "rambo_get_tune: null argument");
     t->seg = h->tune.seg ? h->tune.seg : default_seg(h->RW);
@@ -447,7 +471,8 @@ RAMBO_API int rambo_get_tune(const rambo_t *h, rambo_tune_t *t) {
 
 RAMBO_API int rambo_set_tune(rambo_t *h, const rambo_tune_t *t) {
     if (!h || !t) return fail(RAMBO_EINVAL, "rambo_set_tune: null argument");
-    if (!(t->seg == 1 || t->seg == 2 || t->seg == 4) || (int)h->RW % t->seg || (int)h->RW / t->seg > 64 ||
+    if (!(t->seg == 1 || t->seg == 2 || t->seg == 4) || (int)h->RW % t->seg ||
+        !split_supported(t->seg, (int)h->RW / t->seg) ||
         t->tile < 64 || t->tile % 64 || t->waves_per_cu < 1 || t->waves_per_cu > 64 ||
         !(t->wpb == 1 || t->wpb == 2 || t->wpb == 4) || t->grab < 1 || t->grab > 64)
         return fail(RAMBO_EINVAL, "rambo_set_tune: launch shape out of range");

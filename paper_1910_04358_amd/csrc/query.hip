@@ -10,25 +10,6 @@
 
 namespace rambo {
 
-#define RAMBO_DISPATCH_SEG_G(SEGV, GV, ...)                                  \
-    switch ((SEGV) * 1000 + (GV)) {                                          \
-    case 1001: { constexpr int SEG = 1, G = 1; __VA_ARGS__; } break;         \
-    case 2001: { constexpr int SEG = 2, G = 1; __VA_ARGS__; } break;         \
-    case 4001: { constexpr int SEG = 4, G = 1; __VA_ARGS__; } break;         \
-    case 1002: { constexpr int SEG = 1, G = 2; __VA_ARGS__; } break;         \
-    case 2002: { constexpr int SEG = 2, G = 2; __VA_ARGS__; } break;         \
-    case 4002: { constexpr int SEG = 4, G = 2; __VA_ARGS__; } break;         \
-    case 1004: { constexpr int SEG = 1, G = 4; __VA_ARGS__; } break;         \
-    case 2004: { constexpr int SEG = 2, G = 4; __VA_ARGS__; } break;         \
-    case 4004: { constexpr int SEG = 4, G = 4; __VA_ARGS__; } break;         \
-    case 2008: { constexpr int SEG = 2, G = 8; __VA_ARGS__; } break;         \
-    case 4008: { constexpr int SEG = 4, G = 8; __VA_ARGS__; } break;         \
-    case 2016: { constexpr int SEG = 2, G = 16; __VA_ARGS__; } break;        \
-    case 4016: { constexpr int SEG = 4, G = 16; __VA_ARGS__; } break;        \
-    case 4032: { constexpr int SEG = 4, G = 32; __VA_ARGS__; } break;        \
-    case 4064: { constexpr int SEG = 4, G = 64; __VA_ARGS__; } break;        \
-    default: return fail(RAMBO_EINVAL, "unsupported row split seg=%d lanes=%d", (int)(SEGV), (int)(GV)); \
-    }
 
 // -------------------------------------------------------------------------
 // single k-mer queries: 64 / G terms per wave, then one resolve per term
@@ -167,9 +148,11 @@ int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *
     const uint64_t waves = (n + KPW - 1) / KPW;
     const uint64_t blocks = (waves + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_kmers: batch too large");
-    RAMBO_DISPATCH_SEG_G(seg, G,
-        hipLaunchKernelGGL((k_query_kmers<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, kmers, n,
-                           out, h->d_invalid, h->resolve, use_res));
+#define RAMBO_SPLIT_BODY_                                                                                  \
+    hipLaunchKernelGGL((k_query_kmers<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, kmers, n, out, \
+                       h->d_invalid, h->resolve, use_res)
+    RAMBO_DISPATCH_SPLIT(seg, G)
+#undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());
     return RAMBO_OK;
 }
@@ -189,9 +172,11 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
-    RAMBO_DISPATCH_SEG_G(seg, G,
-        hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs,
-                           offs, n, out, opt, use_res));
+#define RAMBO_SPLIT_BODY_                                                                                  \
+    hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
+                       n, out, opt, use_res)
+    RAMBO_DISPATCH_SPLIT(seg, G)
+#undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());
     return RAMBO_OK;
 }

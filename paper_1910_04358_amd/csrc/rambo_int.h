@@ -61,6 +61,7 @@ struct rambo_s {
     hipStream_t aux = nullptr;  // internal stream (graph capture, sync helpers)
     std::mutex mu;              // guards the graph cache and tuner
     std::map<std::string, std::shared_ptr<rambo::BatchGraph>> graphs;
+    std::shared_ptr<rambo::BatchGraph> last_graph;  // most recently launched
 };
 
 namespace rambo {
@@ -107,6 +108,30 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
 int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
                        hipStream_t s);
 void drop_graphs(rambo_s *h);
+
+// Row split: a lane reads SEG words of a row, G = row_words / SEG lanes share
+// one term. The instantiated (SEG, G) pairs:
+#define RAMBO_SPLITS(X) \
+    X(1, 1) X(2, 1) X(4, 1) X(1, 2) X(2, 2) X(4, 2) X(1, 4) X(2, 4) X(4, 4) X(1, 8) X(2, 8) X(4, 8) \
+    X(1, 16) X(2, 16) X(4, 16) X(1, 32) X(2, 32) X(4, 32) X(1, 64) X(2, 64) X(4, 64)
+
+#define RAMBO_SPLIT_CASE_(S_, G_) case (S_) * 1000 + (G_): { constexpr int SEG = (S_), G = (G_); RAMBO_SPLIT_BODY_; } break;
+
+// Expands RAMBO_SPLIT_BODY_ (defined by the caller, using SEG and G) for the
+// runtime pair (SEGV, GV).
+#define RAMBO_DISPATCH_SPLIT(SEGV, GV)                                                              \
+    switch ((SEGV) * 1000 + (GV)) {                                                                 \
+        RAMBO_SPLITS(RAMBO_SPLIT_CASE_)                                                             \
+    default:                                                                                        \
+        return ::rambo::fail(RAMBO_EINVAL, "unsupported row split seg=%d lanes=%d", (int)(SEGV), (int)(GV)); \
+    }
+
+inline bool split_supported(int seg, int G) {
+#define RAMBO_SPLIT_TEST_(S_, G_) if (seg == (S_) && G == (G_)) return true;
+    RAMBO_SPLITS(RAMBO_SPLIT_TEST_)
+#undef RAMBO_SPLIT_TEST_
+    return false;
+}
 
 // largest power-of-two segment (<= 4 words) that divides a row
 inline int default_seg(uint32_t RW) { return RW >= 4 ? 4 : (int)RW; }

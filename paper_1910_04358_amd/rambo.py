@@ -63,6 +63,7 @@ SIGNATURES = {
     "rambo_autotune": ([_vp, _vp, _vp, _u64, _vp, _vp], _i32),
     "rambo_get_tune": ([_vp, ctypes.POINTER(TuneC)], _i32),
     "rambo_set_tune": ([_vp, ctypes.POINTER(TuneC)], _i32),
+    "rambo_last_batch_ms": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], _i32),
 }
 
 
@@ -78,6 +79,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("librambo.so is not built (python -m paper_1910_04358_amd.build)")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; it must be loaded first so that both share one runtime (and one
+        # view of device memory and streams).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in SIGNATURES.items():
             f = getattr(L, name)
@@ -289,6 +294,12 @@ class Rambo:
         _check(lib().rambo_autotune(self._h, _dptr(seqs, "seqs", (torch.uint8,)), _dptr(offsets, "offsets", _i64()), n,
                                     _dptr(out, "out", _i64()), _stream(stream)))
         return self.get_tune()
+
+    def last_batch_ms(self):
+        """(graph_ms, kernel_ms) of the most recent batched launch."""
+        g, k = ctypes.c_float(), ctypes.c_float()
+        _check(lib().rambo_last_batch_ms(self._h, ctypes.byref(g), ctypes.byref(k)))
+        return g.value, k.value
 
     def get_tune(self) -> Tune:
         t = TuneC()

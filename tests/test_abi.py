@@ -24,7 +24,7 @@ def so():
     if not os.path.exists(rambo.LIB_PATH):
         from paper_1910_04358_amd import build
         build.build()
-    return ctypes.CDLL(rambo.LIB_PATH)
+    return rambo.lib()
 
 
 def test_header_declares_the_boundary():
