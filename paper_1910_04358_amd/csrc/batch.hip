@@ -1,58 +1,35 @@
 // Batched sequence queries: one persistent launch over a work queue of
-// (read, tile of windows) items, replayed from a captured HIP graph, with a
+// (read, tile of windows) items, replayed from captured HIP graphs, with a
 // launch shape chosen by an autotuner.
 //
 // Work order: first tile of every read, then the remaining tiles of all reads
-// in read order. Reads are short (a few hundred bases) and most end after
+// in read order. Reads are short (a few hundred bases) and most end within
 // their first tile (Section 3.3.1: the first FALSE is conclusive), so later
-// tiles mostly find their read already dead and skip their probes. Long reads
-// are spread over many waves; their tiles AND into a per-read mask in global
-// memory (AND is associative and commutative, so the order does not matter)
-// and the wave that finishes a read's last tile resolves it.
+// tiles mostly find their read already dead and skip their probes. A read
+// that fits one tile is finished by the wave that took it, from registers.
+// Longer reads are spread over many waves; their tiles AND into a per-read
+// mask in global memory (AND is associative and commutative, so the order
+// does not matter) and the wave that finishes a read's last tile resolves it.
+//
+// The batch size lives in device memory, so one captured graph serves any
+// batch up to its capacity (the serving loop's slots rely on this).
 #include <algorithm>
-#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
-#include <sstream>
 
-#include "rambo_int.h"
+#include "batch.h"
 
 namespace rambo {
-
-struct BatchBufs {
-    uint32_t *rmask;             // [n][R * RW] running AND per read
-    uint32_t *done;              // [n] finished tiles per read
-    uint64_t *extra;             // [n] tiles beyond the first, per read
-    uint64_t *extra_off;         // [n + 1] exclusive scan of extra
-    unsigned long long *head;    // queue position
-};
-
-struct BatchGraph {
-    uint64_t n = 0;
-    BatchBufs bb{};
-    void *mem = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    // timing events recorded inside the graph: start, before and after the
-    // persistent kernel (null if the runtime cannot capture event records)
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    ~BatchGraph() {
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (mem) (void)hipFree(mem);
-    }
-};
 
 __device__ __forceinline__ uint64_t n_windows(uint64_t beg, uint64_t end) {
     return end >= beg + 31 ? end - beg - 30 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_batch_prep(const uint64_t *__restrict__ offs, uint64_t n, uint32_t mw,
-                                                    uint32_t tile, BatchBufs bb) {
+__global__ __launch_bounds__(256) void k_batch_prep(const uint64_t *__restrict__ offs, const uint64_t *n_ptr,
+                                                    uint32_t mw, uint32_t tile, BatchBufs bb) {
+    const uint64_t n = *n_ptr;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *bb.head = 0;
     if (i >= n) return;
@@ -60,14 +37,17 @@ __global__ __launch_bounds__(256) void k_batch_prep(const uint64_t *__restrict__
     const uint64_t nw = n_windows(beg, end > beg ? end : beg);
     const uint64_t tiles = nw ? (nw + tile - 1) / tile : 1;
     bb.extra[i] = tiles - 1;
-    bb.done[i] = 0;
-    for (uint32_t w = 0; w < mw; w++) bb.rmask[i * mw + w] = 0xFFFFFFFFu;
+    if (tiles > 1) {
+        bb.done[i] = 0;
+        for (uint32_t w = 0; w < mw; w++) bb.rmask[i * mw + w] = 0xFFFFFFFFu;
+    }
 }
 
-// exclusive scan (single workgroup), off[n] = total
-__global__ __launch_bounds__(1024) void k_scan_u64(const uint64_t *__restrict__ v, uint64_t n,
+// exclusive scan of v[0..n) into off[0..n] (off[n] = total), one workgroup
+__global__ __launch_bounds__(1024) void k_scan_u64(const uint64_t *__restrict__ v, const uint64_t *n_ptr,
                                                    uint64_t *__restrict__ off) {
     __shared__ uint64_t part[1024];
+    const uint64_t n = *n_ptr;
     const uint32_t t = threadIdx.x;
     const uint64_t per = (n + 1023) / 1024, lo = t * per, hi = min(n, lo + per);
     uint64_t sum = 0;
@@ -117,9 +97,20 @@ __device__ __forceinline__ bool read_dead(const Index &ix, const uint32_t *rm, u
     return dead;
 }
 
+// the masks staged in LDS have an empty repetition
+__device__ __forceinline__ bool lds_some_rep_empty(const Index &ix, const uint32_t *M, uint32_t lane) {
+    bool empty = false;
+    for (uint32_t r = 0; r < ix.R; r++) {
+        uint32_t o = 0;
+        for (uint32_t w = lane; w < ix.RW; w += 64) o |= M[r * ix.RW + w];
+        empty |= __ballot(o != 0) == 0;
+    }
+    return empty;
+}
+
 template <int SEG, int G>
 __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__restrict__ seqs,
-                                                    const uint64_t *__restrict__ offs, uint64_t n,
+                                                    const uint64_t *__restrict__ offs, const uint64_t *n_ptr,
                                                     uint64_t *__restrict__ out, BatchBufs bb, QueryOpts opt,
                                                     int use_res, uint32_t tile, uint32_t grab) {
     extern __shared__ uint64_t smem64[];
@@ -130,6 +121,7 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
     uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * per_wave;
     uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + mwords) : nullptr;
 
+    const uint64_t n = *n_ptr;
     const uint64_t total = n + bb.extra_off[n];
     uint64_t issued = 0;
     for (;;) {
@@ -154,11 +146,12 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
             const uint64_t nwin = n_windows(beg, end);
             const uint64_t ntiles = nwin ? (nwin + tile - 1) / tile : 1;
             uint32_t *rm = bb.rmask + i * mw;
+            uint64_t *o = out + i * ix.W;
 
-            bool skip = c > 0 && opt.early_exit && read_dead(ix, rm, lane);
+            const bool skip = c > 0 && opt.early_exit && read_dead(ix, rm, lane);
+            Seg<SEG> acc[MAXR];
+            set_ones(acc);
             if (!skip) {
-                Seg<SEG> acc[MAXR];
-                set_ones(acc);
                 const uint64_t w_hi = min(nwin, (c + 1) * (uint64_t)tile);
                 for (uint64_t w = c * (uint64_t)tile; w < w_hi; w += 64) {
                     const uint64_t p = beg + w + lane;
@@ -175,14 +168,34 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
                     issued += __popcll(__ballot(valid));
                     if (opt.early_exit && some_rep_empty<SEG, G>(acc, ix.R)) break;
                 }
-                if (lane < (uint32_t)G) {
+            }
+            if (ntiles == 1) {
+                // the whole read was in this tile: resolve from registers
+                if (some_rep_empty<SEG, G>(acc, ix.R)) {
+                    write_zeros(o, ix.W, lane);
+                } else {
+                    if (lane < (uint32_t)G) {
 #pragma unroll
-                    for (int r = 0; r < MAXR; r++)
-                        if (r < (int)ix.R)
+                        for (int r = 0; r < MAXR; r++)
+                            if (r < (int)ix.R)
 #pragma unroll
-                            for (int s = 0; s < SEG; s++)
-                                if (acc[r].w[s] != 0xFFFFFFFFu) atomicAnd(rm + r * ix.RW + lane * SEG + s, acc[r].w[s]);
+                                for (int s = 0; s < SEG; s++) M[r * ix.RW + lane * SEG + s] = acc[r].w[s];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    resolve(ix, M, res, o, lane, opt.rmode);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                continue;
+            }
+            if (!skip && lane < (uint32_t)G) {
+#pragma unroll
+                for (int r = 0; r < MAXR; r++)
+                    if (r < (int)ix.R)
+#pragma unroll
+                        for (int s = 0; s < SEG; s++)
+                            if (acc[r].w[s] != 0xFFFFFFFFu) atomicAnd(rm + r * ix.RW + lane * SEG + s, acc[r].w[s]);
             }
             __threadfence();
             uint32_t prev = 0;
@@ -194,14 +207,7 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
                 for (uint32_t w = lane; w < mw; w += 64) M[w] = load_coherent(rm + w);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                bool empty = false;
-                for (uint32_t r = 0; r < ix.R; r++) {
-                    uint32_t o = 0;
-                    for (uint32_t w = lane; w < ix.RW; w += 64) o |= M[r * ix.RW + w];
-                    empty |= __ballot(o != 0) == 0;
-                }
-                uint64_t *o = out + i * ix.W;
-                if (empty) write_zeros(o, ix.W, lane);
+                if (lds_some_rep_empty(ix, M, lane)) write_zeros(o, ix.W, lane);
                 else resolve(ix, M, res, o, lane, opt.rmode);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -213,16 +219,19 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
 
 static constexpr uint32_t kMaxLds = 64 * 1024;
 
+static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint64_t *offs, hipStream_t s) {
+    const uint32_t mw = h->R * h->RW;
+    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, offs, bg.d_n, mw,
+                       (uint32_t)tu.tile, bg.bb);
+    hipLaunchKernelGGL(k_scan_u64, dim3(1), dim3(1024), 0, s, bg.bb.extra, bg.d_n, bg.bb.extra_off);
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
 
-// Enqueue the batched form's kernels on stream s (captured into the graph).
-static int enqueue_batched(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_t *seqs, const uint64_t *offs,
-                           uint64_t n, uint64_t *out, hipStream_t s) {
+static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_t *seqs, const uint64_t *offs,
+                        uint64_t *out, hipStream_t s) {
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
-    if (bg.ev[0]) HIP_CHECK(hipEventRecord(bg.ev[0], s));
-    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, offs, n, mw,
-                       (uint32_t)tu.tile, bg.bb);
-    hipLaunchKernelGGL(k_scan_u64, dim3(1), dim3(1024), 0, s, bg.bb.extra, n, bg.bb.extra_off);
     const int G = (int)h->RW / tu.seg;
     const uint32_t mwords = (mw + 1) & ~1u;
     int use_res = 1;
@@ -233,57 +242,75 @@ static int enqueue_batched(rambo_s *h, const Tune &tu, BatchGraph &bg, const uin
     }
     const unsigned blocks = (unsigned)std::max(1, h->n_cu * tu.waves_per_cu / tu.wpb);
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
-    if (bg.ev[1]) HIP_CHECK(hipEventRecord(bg.ev[1], s));
 #define RAMBO_SPLIT_BODY_                                                                                  \
-    hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs, n, out,       \
+    hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs, bg.d_n, out, \
                        bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab)
     RAMBO_DISPATCH_SPLIT(tu.seg, G)
 #undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());
-    if (bg.ev[2]) HIP_CHECK(hipEventRecord(bg.ev[2], s));
     return RAMBO_OK;
 }
 
-static int make_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
-                      uint64_t *out, std::shared_ptr<BatchGraph> &res) {
-    auto bg = std::make_shared<BatchGraph>();
-    bg->n = n;
-    const size_t mw = (size_t)h->R * h->RW;
-    const size_t bytes_mask = ((n * mw * 4) + 255) & ~(size_t)255;
-    const size_t bytes_done = ((n * 4) + 255) & ~(size_t)255;
-    const size_t bytes_extra = ((n * 8) + 255) & ~(size_t)255;
-    const size_t bytes_off = (((n + 1) * 8) + 255) & ~(size_t)255;
-    HIP_CHECK(hipMalloc(&bg->mem, bytes_mask + bytes_done + bytes_extra + bytes_off + 256));
-    char *p = (char *)bg->mem;
-    bg->bb.rmask = (uint32_t *)p; p += bytes_mask;
-    bg->bb.done = (uint32_t *)p; p += bytes_done;
-    bg->bb.extra = (uint64_t *)p; p += bytes_extra;
-    bg->bb.extra_off = (uint64_t *)p; p += bytes_off;
-    bg->bb.head = (unsigned long long *)p;
-    for (auto &ev : bg->ev) HIP_CHECK(hipEventCreate(&ev));
-    hipGraph_t g = nullptr;
-    int st = RAMBO_OK;
-    hipError_t e = hipSuccess;
-    for (int attempt = 0; attempt < 2; attempt++) {
-        HIP_CHECK(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
-        st = enqueue_batched(h, tu, *bg, seqs, offs, n, out, h->aux);
-        g = nullptr;
-        e = hipStreamEndCapture(h->aux, &g);
-        if (st == RAMBO_OK && e == hipSuccess) break;
-        if (g) (void)hipGraphDestroy(g);
-        g = nullptr;
-        (void)hipGetLastError();
-        // retry without the timing events
-        for (auto &ev : bg->ev) {
-            if (ev) (void)hipEventDestroy(ev);
-            ev = nullptr;
-        }
+BatchGraph::~BatchGraph() {
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (exec_prep) (void)hipGraphExecDestroy(exec_prep);
+    if (exec_main) (void)hipGraphExecDestroy(exec_main);
+    if (graph_prep) (void)hipGraphDestroy(graph_prep);
+    if (graph_main) (void)hipGraphDestroy(graph_main);
+    if (mem) (void)hipFree(mem);
+}
+
+static int capture(rambo_s *h, hipGraph_t *g, hipGraphExec_t *exec, const std::function<int(hipStream_t)> &body) {
+    HIP_CHECK(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
+    int st = body(h->aux);
+    hipGraph_t gg = nullptr;
+    hipError_t e = hipStreamEndCapture(h->aux, &gg);
+    if (st != RAMBO_OK) {
+        if (gg) (void)hipGraphDestroy(gg);
+        return st;
     }
-    if (st != RAMBO_OK) return st;
     if (e != hipSuccess) return fail(RAMBO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    bg->graph = g;
-    HIP_CHECK(hipGraphInstantiate(&bg->exec, g, nullptr, nullptr, 0));
+    *g = gg;
+    HIP_CHECK(hipGraphInstantiate(exec, gg, nullptr, nullptr, 0));
+    return RAMBO_OK;
+}
+
+int make_batch_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t cap,
+                     uint64_t *out, const uint64_t *n_value, std::shared_ptr<BatchGraph> &res) {
+    auto bg = std::make_shared<BatchGraph>();
+    bg->cap = cap;
+    bg->tune = tu;
+    const size_t mw = (size_t)h->R * h->RW;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b_mask = al(cap * mw * 4), b_done = al(cap * 4), b_extra = al(cap * 8), b_off = al((cap + 1) * 8);
+    HIP_CHECK(hipMalloc(&bg->mem, b_mask + b_done + b_extra + b_off + 512));
+    char *p = (char *)bg->mem;
+    bg->bb.rmask = (uint32_t *)p; p += b_mask;
+    bg->bb.done = (uint32_t *)p; p += b_done;
+    bg->bb.extra = (uint64_t *)p; p += b_extra;
+    bg->bb.extra_off = (uint64_t *)p; p += b_off;
+    bg->bb.head = (unsigned long long *)p; p += 256;
+    bg->d_n = (uint64_t *)p;
+    if (n_value) HIP_CHECK(hipMemcpy(bg->d_n, n_value, 8, hipMemcpyHostToDevice));
+    for (auto &e : bg->ev) HIP_CHECK(hipEventCreate(&e));
+    int st = capture(h, &bg->graph_prep, &bg->exec_prep,
+                     [&](hipStream_t s) { return enqueue_prep(h, tu, *bg, offs, s); });
+    if (st == RAMBO_OK)
+        st = capture(h, &bg->graph_main, &bg->exec_main,
+                     [&](hipStream_t s) { return enqueue_main(h, tu, *bg, seqs, offs, out, s); });
+    if (st != RAMBO_OK) return st;
     res = bg;
+    return RAMBO_OK;
+}
+
+int launch_batch_graph(rambo_s *h, BatchGraph &bg, hipStream_t s) {
+    (void)h;
+    HIP_CHECK(hipEventRecord(bg.ev[0], s));
+    HIP_CHECK(hipGraphLaunch(bg.exec_prep, s));
+    HIP_CHECK(hipEventRecord(bg.ev[1], s));
+    HIP_CHECK(hipGraphLaunch(bg.exec_main, s));
+    HIP_CHECK(hipEventRecord(bg.ev[2], s));
     return RAMBO_OK;
 }
 
@@ -297,25 +324,20 @@ static std::string graph_key(const Tune &tu, const uint8_t *seqs, const uint64_t
 static int run_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
                      uint64_t *out, hipStream_t s) {
     std::shared_ptr<BatchGraph> bg;
-    {
-        std::lock_guard<std::mutex> g(h->mu);
-        const std::string key = graph_key(tu, seqs, offs, n, out);
-        auto it = h->graphs.find(key);
-        if (it != h->graphs.end()) {
-            bg = it->second;
-        } else {
-            if (h->graphs.size() >= 16) h->graphs.clear();
-            int st = make_graph(h, tu, seqs, offs, n, out, bg);
-            if (st != RAMBO_OK) return st;
-            h->graphs[key] = bg;
-        }
+    std::lock_guard<std::mutex> g(h->mu);
+    const std::string key = graph_key(tu, seqs, offs, n, out);
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        bg = it->second;
+    } else {
+        if (h->graphs.size() >= 16) h->graphs.clear();
+        int st = make_batch_graph(h, tu, seqs, offs, n, out, &n, bg);
+        if (st != RAMBO_OK) return st;
+        h->graphs[key] = bg;
     }
-    HIP_CHECK(hipGraphLaunch(bg->exec, s));
-    {
-        std::lock_guard<std::mutex> g(h->mu);
-        h->last_graph = bg;
-    }
-    return RAMBO_OK;
+    int st = launch_batch_graph(h, *bg, s);
+    if (st == RAMBO_OK) h->last_graph = bg;
+    return st;
 }
 
 void drop_graphs(rambo_s *h) {
@@ -327,6 +349,13 @@ void drop_graphs(rambo_s *h) {
 // autotuner: coordinate search over the launch shape on the caller's batch
 // (every candidate computes the same bits), cached per index shape.
 // ---------------------------------------------------------------------------
+bool tune_valid(const rambo_s *h, const Tune &t) {
+    return (t.seg == 1 || t.seg == 2 || t.seg == 4) && (int)h->RW % t.seg == 0 &&
+           split_supported(t.seg, (int)h->RW / t.seg) && t.tile >= 64 && t.tile % 64 == 0 && t.tile <= (1 << 20) &&
+           t.waves_per_cu >= 1 && t.waves_per_cu <= 64 && (t.wpb == 1 || t.wpb == 2 || t.wpb == 4) && t.grab >= 1 &&
+           t.grab <= 64;
+}
+
 static std::string tune_key(const rambo_s *h) {
     hipDeviceProp_t prop;
     const char *arch = "gpu";
@@ -336,7 +365,7 @@ static std::string tune_key(const rambo_s *h) {
              h->eta, (unsigned long long)h->m, h->early_exit);
     std::string s = buf;
     for (auto &c : s)
-        if (c == ':') c = '_';
+        if (c == ':' || c == '|') c = '_';
     return s;
 }
 
@@ -349,7 +378,8 @@ static bool tune_cache_load(rambo_s *h) {
         const size_t bar = line.find('|');
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         Tune t;
-        if (sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.seg, &t.tile, &t.waves_per_cu, &t.wpb, &t.grab) == 5) {
+        if (sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.seg, &t.tile, &t.waves_per_cu, &t.wpb, &t.grab) == 5 &&
+            tune_valid(h, t)) {
             h->tune = t;
             return true;
         }
@@ -389,30 +419,31 @@ static int time_candidate(rambo_s *h, const Tune &tu, const uint8_t *seqs, const
     return st;
 }
 
-static int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out, hipStream_t s) {
+int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out, hipStream_t s) {
     Tune best = h->tune;
     best.seg = default_seg(h->RW);
     float best_ms = 0;
     int st = time_candidate(h, best, seqs, offs, n, out, s, best_ms);
     if (st != RAMBO_OK) return st;
     auto consider = [&](Tune t) -> int {
-        if ((int)h->RW % t.seg || !split_supported(t.seg, (int)h->RW / t.seg)) return RAMBO_OK;
+        if (!tune_valid(h, t)) return RAMBO_OK;
         float ms = 0;
         int st2 = time_candidate(h, t, seqs, offs, n, out, s, ms);
         if (st2 != RAMBO_OK) return st2;
-        if (ms < best_ms * 0.98f) { best = t; best_ms = ms; }
+        if (ms < best_ms * 0.98f) {
+            best = t;
+            best_ms = ms;
+        }
         return RAMBO_OK;
     };
-    for (int tile : {64, 256, 512}) { Tune t = best; t.tile = tile; if ((st = consider(t))) return st; }
+    for (int tile : {64, 256, 512, 1024}) { Tune t = best; t.tile = tile; if ((st = consider(t))) return st; }
     for (int wpc : {4, 16, 32}) { Tune t = best; t.waves_per_cu = wpc; if ((st = consider(t))) return st; }
     for (int seg : {1, 2, 4}) { Tune t = best; t.seg = seg; if (t.seg != best.seg && (st = consider(t))) return st; }
     for (int grab : {2, 4}) { Tune t = best; t.grab = grab; if ((st = consider(t))) return st; }
-    for (int wpb : {1, 2}) { Tune t = best; t.wpb = wpb; if (t.waves_per_cu % wpb == 0 && (st = consider(t))) return st; }
+    for (int wpb : {1, 2}) { Tune t = best; t.wpb = wpb; if ((st = consider(t))) return st; }
+    std::lock_guard<std::mutex> g(h->mu);
     h->tune = best;
-    {
-        std::lock_guard<std::mutex> g(h->mu);
-        drop_graphs(h);  // keep only graphs of the chosen shape
-    }
+    drop_graphs(h);  // keep only graphs of the chosen shape
     return RAMBO_OK;
 }
 
@@ -429,7 +460,12 @@ int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, ui
         }
         h->tuned = true;
     }
-    return run_graph(h, h->tune, seqs, offs, n, out, s);
+    Tune tu;
+    {
+        std::lock_guard<std::mutex> g(h->mu);
+        tu = h->tune;
+    }
+    return run_graph(h, tu, seqs, offs, n, out, s);
 }
 
 }  // namespace rambo
@@ -451,7 +487,7 @@ RAMBO_API int rambo_last_batch_ms(rambo_t *h, float *graph_ms, float *kernel_ms)
         std::lock_guard<std::mutex> g(h->mu);
         bg = h->last_graph;
     }
-    if (!bg || !bg->ev[0]) return fail(RAMBO_EINVAL, "rambo_last_batch_ms: no timed batched launch");
+    if (!bg) return fail(RAMBO_EINVAL, "rambo_last_batch_ms: no batched launch yet");
     HIP_CHECK(hipEventSynchronize(bg->ev[2]));
     HIP_CHECK(hipEventElapsedTime(graph_ms, bg->ev[0], bg->ev[2]));
     HIP_CHECK(hipEventElapsedTime(kernel_ms, bg->ev[1], bg->ev[2]));
@@ -471,17 +507,15 @@ RAMBO_API int rambo_get_tune(const rambo_t *h, rambo_tune_t *t) {
 
 RAMBO_API int rambo_set_tune(rambo_t *h, const rambo_tune_t *t) {
     if (!h || !t) return fail(RAMBO_EINVAL, "rambo_set_tune: null argument");
-    if (!(t->seg == 1 || t->seg == 2 || t->seg == 4) || (int)h->RW % t->seg ||
-        !split_supported(t->seg, (int)h->RW / t->seg) ||
-        t->tile < 64 || t->tile % 64 || t->waves_per_cu < 1 || t->waves_per_cu > 64 ||
-        !(t->wpb == 1 || t->wpb == 2 || t->wpb == 4) || t->grab < 1 || t->grab > 64)
-        return fail(RAMBO_EINVAL, "rambo_set_tune: launch shape out of range");
+    Tune tu;
+    tu.seg = t->seg;
+    tu.tile = t->tile;
+    tu.waves_per_cu = t->waves_per_cu;
+    tu.wpb = t->wpb;
+    tu.grab = t->grab;
+    if (!tune_valid(h, tu)) return fail(RAMBO_EINVAL, "rambo_set_tune: launch shape out of range");
     std::lock_guard<std::mutex> g(h->mu);
-    h->tune.seg = t->seg;
-    h->tune.tile = t->tile;
-    h->tune.waves_per_cu = t->waves_per_cu;
-    h->tune.wpb = t->wpb;
-    h->tune.grab = t->grab;
+    h->tune = tu;
     h->tuned = true;
     drop_graphs(h);
     return RAMBO_OK;
