@@ -14,8 +14,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librambo.so")
+MICRO = os.path.join(HERE, "libmicro.so")
 
-SOURCES = ["api.hip", "build.hip", "query.hip", "batch.hip"]
+SOURCES = ["api.hip", "build.hip", "query.hip", "batch.hip", "scan.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RAMBO_OFFLOAD_ARCH", "gfx950")
@@ -48,8 +49,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-4000:]))
     os.replace(tmp, LIB)
+    # random-access microbenchmarks: a library of their own
+    tmp = MICRO + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *FLAGS, "-shared", "-o", tmp, os.path.join(CSRC, "micro.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for micro.hip:\n%s" % r.stderr[-4000:])
+    os.replace(tmp, MICRO)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", MICRO)
     return LIB
 
 

@@ -23,6 +23,7 @@ struct BatchGraph {
     Tune tune;
     BatchBufs bb{};
     uint64_t *d_n = nullptr;
+    uint64_t *parts = nullptr;  // scan scratch
     void *mem = nullptr;
     hipGraph_t graph_prep = nullptr, graph_main = nullptr;
     hipGraphExec_t exec_prep = nullptr, exec_main = nullptr;

@@ -20,6 +20,7 @@
 #include <fstream>
 
 #include "batch.h"
+#include "scan.h"
 
 namespace rambo {
 
@@ -41,31 +42,6 @@ __global__ __launch_bounds__(256) void k_batch_prep(const uint64_t *__restrict__
         bb.done[i] = 0;
         for (uint32_t w = 0; w < mw; w++) bb.rmask[i * mw + w] = 0xFFFFFFFFu;
     }
-}
-
-// exclusive scan of v[0..n) into off[0..n] (off[n] = total), one workgroup
-__global__ __launch_bounds__(1024) void k_scan_u64(const uint64_t *__restrict__ v, const uint64_t *n_ptr,
-                                                   uint64_t *__restrict__ off) {
-    __shared__ uint64_t part[1024];
-    const uint64_t n = *n_ptr;
-    const uint32_t t = threadIdx.x;
-    const uint64_t per = (n + 1023) / 1024, lo = t * per, hi = min(n, lo + per);
-    uint64_t sum = 0;
-    for (uint64_t i = lo; i < hi; i++) sum += v[i];
-    part[t] = sum;
-    __syncthreads();
-    for (uint32_t d = 1; d < 1024; d <<= 1) {
-        const uint64_t x = t >= d ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
-    }
-    uint64_t run = part[t] - sum;
-    for (uint64_t i = lo; i < hi; i++) {
-        off[i] = run;
-        run += v[i];
-    }
-    if (t == 1023) off[n] = part[1023];
 }
 
 // largest i < n with off[i] <= u, by a 64-way search (one load per lane per round)
@@ -159,14 +135,10 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
                     const uint32_t c1 = (lane < 30 && p + 64 < end) ? seqs[p + 64] : 0u;
                     const Window wv = extract_windows(c0, c1, lane);
                     const bool valid = wv.valid && (w + lane < w_hi);
-                    Seg<SEG> cm[MAXR];
-                    probe_chunk<SEG, G>(ix, wv, valid, lane, cm);
-#pragma unroll
-                    for (int r = 0; r < MAXR; r++)
-#pragma unroll
-                        for (int s = 0; s < SEG; s++) acc[r].w[s] &= cm[r].w[s];
-                    issued += __popcll(__ballot(valid));
-                    if (opt.early_exit && some_rep_empty<SEG, G>(acc, ix.R)) break;
+                    bool dead;
+                    const uint32_t reps = probe_step<SEG, G>(ix, wv, valid, lane, acc, opt.early_exit != 0, &dead);
+                    issued += (uint64_t)__popcll(__ballot(valid)) * reps;
+                    if (dead) break;
                 }
             }
             if (ntiles == 1) {
@@ -214,7 +186,7 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
             }
         }
     }
-    if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.R * ix.eta));
+    if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
 }
 
 static constexpr uint32_t kMaxLds = 64 * 1024;
@@ -223,9 +195,8 @@ static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint64
     const uint32_t mw = h->R * h->RW;
     hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, offs, bg.d_n, mw,
                        (uint32_t)tu.tile, bg.bb);
-    hipLaunchKernelGGL(k_scan_u64, dim3(1), dim3(1024), 0, s, bg.bb.extra, bg.d_n, bg.bb.extra_off);
     HIP_CHECK(hipGetLastError());
-    return RAMBO_OK;
+    return launch_exclusive_scan(bg.bb.extra, bg.d_n, bg.cap, bg.bb.extra_off, bg.parts, s);
 }
 
 static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_t *seqs, const uint64_t *offs,
@@ -284,8 +255,10 @@ int make_batch_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint
     const size_t mw = (size_t)h->R * h->RW;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t b_mask = al(cap * mw * 4), b_done = al(cap * 4), b_extra = al(cap * 8), b_off = al((cap + 1) * 8);
-    HIP_CHECK(hipMalloc(&bg->mem, b_mask + b_done + b_extra + b_off + 512));
+    const size_t b_parts = al(scan_parts_needed(cap) * 8);
+    HIP_CHECK(hipMalloc(&bg->mem, b_mask + b_done + b_extra + b_off + b_parts + 512));
     char *p = (char *)bg->mem;
+    bg->parts = (uint64_t *)p; p += b_parts;
     bg->bb.rmask = (uint32_t *)p; p += b_mask;
     bg->bb.done = (uint32_t *)p; p += b_done;
     bg->bb.extra = (uint64_t *)p; p += b_extra;

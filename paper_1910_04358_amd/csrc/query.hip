@@ -7,6 +7,7 @@
 // stops at the first repetition whose mask is empty. The per-document AND
 // over repetitions ("resolve") runs on the masks staged in LDS.
 #include "rambo_int.h"
+#include "scan.h"
 
 namespace rambo {
 
@@ -105,16 +106,12 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
         const uint32_t c1 = (lane < 30 && p + 64 < end) ? seqs[p + 64] : 0u;
         const Window wv = extract_windows(c0, c1, lane);
         const bool valid = wv.valid && (c + lane < nwin);
-        Seg<SEG> cm[MAXR];
-        probe_chunk<SEG, G>(ix, wv, valid, lane, cm);
-#pragma unroll
-        for (int r = 0; r < MAXR; r++)
-#pragma unroll
-            for (int s = 0; s < SEG; s++) acc[r].w[s] &= cm[r].w[s];
-        issued += __popcll(__ballot(valid));
-        if (opt.early_exit && some_rep_empty<SEG, G>(acc, ix.R)) break;
+        bool dead;
+        const uint32_t reps = probe_step<SEG, G>(ix, wv, valid, lane, acc, opt.early_exit != 0, &dead);
+        issued += (uint64_t)__popcll(__ballot(valid)) * reps;
+        if (dead) break;
     }
-    if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.R * ix.eta));
+    if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
     uint64_t *o = out + read * ix.W;
     if (some_rep_empty<SEG, G>(acc, ix.R)) {
         write_zeros(o, ix.W, lane);
@@ -196,30 +193,6 @@ __global__ __launch_bounds__(256) void k_count_bits(const uint64_t *__restrict__
     if (lane == 0) counts[i] = c;
 }
 
-// exclusive scan of counts[0..n) into off[0..n], one workgroup
-__global__ __launch_bounds__(1024) void k_scan(const uint64_t *__restrict__ counts, uint64_t n,
-                                               uint64_t *__restrict__ off) {
-    __shared__ uint64_t part[1024];
-    const uint32_t t = threadIdx.x;
-    const uint64_t per = (n + 1023) / 1024, lo = t * per, hi = min(n, lo + per);
-    uint64_t sum = 0;
-    for (uint64_t i = lo; i < hi; i++) sum += counts[i];
-    part[t] = sum;
-    __syncthreads();
-    for (uint32_t d = 1; d < 1024; d <<= 1) {
-        const uint64_t v = t >= d ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint64_t run = part[t] - sum;
-    for (uint64_t i = lo; i < hi; i++) {
-        off[i] = run;
-        run += counts[i];
-    }
-    if (t == 1023) off[n] = part[1023];
-}
-
 __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ bits, uint64_t n, uint32_t W,
                                                  const uint64_t *__restrict__ off, uint32_t *__restrict__ ids) {
     const uint32_t lane = threadIdx.x & 63;
@@ -256,10 +229,18 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
         return RAMBO_OK;
     }
     uint64_t *counts = nullptr;
-    HIP_CHECK(hipMallocAsync((void **)&counts, n * 8, s));
+    const uint64_t nparts = scan_parts_needed(n);
+    HIP_CHECK(hipMallocAsync((void **)&counts, (n + nparts + 1) * 8, s));
+    uint64_t *parts = counts + n, *d_n = parts + nparts;
+    const uint64_t n_host = n;
+    HIP_CHECK(hipMemcpyAsync(d_n, &n_host, 8, hipMemcpyHostToDevice, s));
     const unsigned blocks = (unsigned)((n + 3) / 4);
     hipLaunchKernelGGL(k_count_bits, dim3(blocks), dim3(256), 0, s, bits, n, W, counts);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, n, id_off);
+    int sst = launch_exclusive_scan(counts, d_n, n, id_off, parts, s);
+    if (sst != RAMBO_OK) {
+        (void)hipFreeAsync(counts, s);
+        return sst;
+    }
     hipError_t e = hipMemcpyAsync(&total, id_off + n, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

@@ -210,25 +210,64 @@ __device__ __forceinline__ bool some_rep_empty(const Seg<SEG> (&acc)[MAXR], uint
     return empty;
 }
 
-// One step of 64 windows: every valid window's term is probed; the masks of
-// the step's terms are ANDed across the wave (G lanes share a term).
-template <int SEG, int G>
-__device__ __forceinline__ void probe_chunk(const Index &ix, const Window &wv, bool valid, uint32_t lane,
-                                            Seg<SEG> (&cm)[MAXR]) {
-    set_ones(cm);
-    if constexpr (G == 1) {
-        if (valid) probe_and<SEG>(ix, wv.canon, 0, cm);
-    } else {
-        constexpr int KPW = 64 / G;
-#pragma unroll 1
-        for (int sub = 0; sub < G; sub++) {
-            const int src = sub * KPW + (int)(lane / G);
-            const uint64_t x = __shfl(wv.canon, src);
-            const int v = __shfl((int)valid, src);
-            if (v) probe_and<SEG>(ix, x, lane % G, cm);
+// Probe term x in repetition r only: AND over j of rows (r, h_{r,j}(x)),
+// this lane's segment.
+template <int SEG>
+__device__ __forceinline__ void probe_rep(const Index &ix, uint64_t x, uint32_t seg, int r, Seg<SEG> &acc) {
+#pragma unroll
+    for (int j = 0; j < MAXETA; j++) {
+        if (j < (int)ix.eta) {
+            const uint64_t pos = bloom_pos(ix, (uint32_t)r * ix.eta + j, x);
+            const Seg<SEG> v = load_seg<SEG>(row_ptr(ix, r, pos) + seg * SEG);
+#pragma unroll
+            for (int s = 0; s < SEG; s++) acc.w[s] &= v.w[s];
         }
     }
-    reduce_groups<SEG, G>(cm, ix.R);
+}
+
+// One step of 64 windows, repetition by repetition: every valid window's
+// term is probed in repetition r, the masks of the step's terms are ANDed
+// across the wave (G lanes share a term) into the read's running mask
+// acc[r]. With early exit, the step stops at the first repetition whose
+// running mask is empty: the read's answer is then empty whatever the other
+// repetitions hold (Section 3.3.1). Returns the number of repetitions
+// probed; *dead tells whether the read ended.
+template <int SEG, int G>
+__device__ __forceinline__ uint32_t probe_step(const Index &ix, const Window &wv, bool valid, uint32_t lane,
+                                               Seg<SEG> (&acc)[MAXR], bool early_exit, bool *dead) {
+    const uint64_t group0 = (G >= 64) ? ~0ULL : ((1ULL << G) - 1);
+    *dead = false;
+#pragma unroll
+    for (int r = 0; r < MAXR; r++) {
+        if (r < (int)ix.R) {
+            Seg<SEG> cm;
+#pragma unroll
+            for (int s = 0; s < SEG; s++) cm.w[s] = 0xFFFFFFFFu;
+            if constexpr (G == 1) {
+                if (valid) probe_rep<SEG>(ix, wv.canon, 0, r, cm);
+            } else {
+                constexpr int KPW = 64 / G;
+#pragma unroll 1
+                for (int sub = 0; sub < G; sub++) {
+                    const int src = sub * KPW + (int)(lane / G);
+                    const uint64_t x = __shfl(wv.canon, src);
+                    const int v = __shfl((int)valid, src);
+                    if (v) probe_rep<SEG>(ix, x, lane % G, r, cm);
+                }
+            }
+            uint32_t o = 0;
+#pragma unroll
+            for (int s = 0; s < SEG; s++) {
+                acc[r].w[s] &= and_across_groups<G>(cm.w[s]);
+                o |= acc[r].w[s];
+            }
+            if (early_exit && (__ballot(o != 0) & group0) == 0) {
+                *dead = true;
+                return (uint32_t)r + 1;
+            }
+        }
+    }
+    return ix.R;
 }
 
 // ---------------------------------------------------------------------------
