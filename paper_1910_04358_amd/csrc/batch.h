@@ -20,6 +20,7 @@ struct BatchBufs {
 // read from d_n on the device, so the graphs serve any n <= cap.
 struct BatchGraph {
     uint64_t cap = 0;
+    unsigned blocks = 0;  // workgroups of the persistent launch
     Tune tune;
     BatchBufs bb{};
     uint64_t *d_n = nullptr;

@@ -211,11 +211,17 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_
         use_res = 0;
         lds = (size_t)tu.wpb * mwords * 4;
     }
-    const unsigned blocks = (unsigned)std::max(1, h->n_cu * tu.waves_per_cu / tu.wpb);
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
+    // a persistent grid must be resident: never more workgroups than fit
 #define RAMBO_SPLIT_BODY_                                                                                  \
-    hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs, bg.d_n, out, \
-                       bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab)
+    {                                                                                                      \
+        int fit = 0;                                                                                       \
+        HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_batch_main<SEG, G>, 64 * tu.wpb, lds)); \
+        const int per_cu = std::max(1, std::min(fit, tu.waves_per_cu / tu.wpb));                         \
+        bg.blocks = (unsigned)(h->n_cu * per_cu);                                                          \
+        hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(bg.blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs,  \
+                           bg.d_n, out, bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab);        \
+    }
     RAMBO_DISPATCH_SPLIT(tu.seg, G)
 #undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());
@@ -398,11 +404,19 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
     float best_ms = 0;
     int st = time_candidate(h, best, seqs, offs, n, out, s, best_ms);
     if (st != RAMBO_OK) return st;
+    const char *vb = getenv("RAMBO_TUNE_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
+    if (verbose)
+        fprintf(stderr, "rambo autotune: seg=%d tile=%d waves/CU=%d wpb=%d grab=%d -> %.3f ms (start)\n", best.seg,
+                best.tile, best.waves_per_cu, best.wpb, best.grab, best_ms);
     auto consider = [&](Tune t) -> int {
         if (!tune_valid(h, t)) return RAMBO_OK;
         float ms = 0;
         int st2 = time_candidate(h, t, seqs, offs, n, out, s, ms);
         if (st2 != RAMBO_OK) return st2;
+        if (verbose)
+            fprintf(stderr, "rambo autotune: seg=%d tile=%d waves/CU=%d wpb=%d grab=%d -> %.3f ms\n", t.seg, t.tile,
+                    t.waves_per_cu, t.wpb, t.grab, ms);
         if (ms < best_ms * 0.98f) {
             best = t;
             best_ms = ms;
@@ -410,9 +424,9 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
         return RAMBO_OK;
     };
     for (int tile : {64, 256, 512, 1024}) { Tune t = best; t.tile = tile; if ((st = consider(t))) return st; }
-    for (int wpc : {4, 16, 32}) { Tune t = best; t.waves_per_cu = wpc; if ((st = consider(t))) return st; }
+    for (int wpc : {4, 12, 16, 24, 32}) { Tune t = best; t.waves_per_cu = wpc; if ((st = consider(t))) return st; }
     for (int seg : {1, 2, 4}) { Tune t = best; t.seg = seg; if (t.seg != best.seg && (st = consider(t))) return st; }
-    for (int grab : {2, 4}) { Tune t = best; t.grab = grab; if ((st = consider(t))) return st; }
+    for (int grab : {2, 4, 16}) { Tune t = best; t.grab = grab; if ((st = consider(t))) return st; }
     for (int wpb : {1, 2}) { Tune t = best; t.wpb = wpb; if ((st = consider(t))) return st; }
     std::lock_guard<std::mutex> g(h->mu);
     h->tune = best;

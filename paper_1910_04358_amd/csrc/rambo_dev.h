@@ -181,6 +181,9 @@ template <int G>
 __device__ __forceinline__ uint32_t and_across_groups(uint32_t v) {
 #pragma unroll
     for (int off = G; off < 64; off <<= 1) v &= __shfl_xor(v, off);
+    // one lane per term: the result is the same in every lane; keeping it in
+    // a scalar register frees vector registers for loads in flight
+    if constexpr (G == 1) v = __builtin_amdgcn_readfirstlane(v);
     return v;
 }
 
