@@ -239,6 +239,78 @@ int rambo_get_tune(const rambo_t *h, rambo_tune_t *out);
 int rambo_last_batch_ms(rambo_t *h, float *graph_ms, float *kernel_ms);
 int rambo_set_tune(rambo_t *h, const rambo_tune_t *t);
 
+/* ---------------------------------------------------------------------- */
+/* Serving loop (continuous batching)                                      */
+/* ---------------------------------------------------------------------- */
+
+typedef struct rambo_server_s rambo_server_t;
+
+enum {
+    RAMBO_SERVE_CONTINUOUS = 0, /* batches form from whatever is pending while
+                                   up to `slots` earlier batches run; batched
+                                   form replayed from per-slot graphs */
+    RAMBO_SERVE_SERIAL = 1,     /* baseline: take everything that has arrived,
+                                   run the plain kernel, wait, repeat */
+};
+
+typedef struct {
+    uint64_t budget_bytes;    /* admission budget: device bytes of in-flight
+                                 reads and their result state (read bytes +
+                                 8 + W*8 + R*row_words*4 + 16 per read) */
+    uint32_t slots;           /* batches in flight at once (1..64) */
+    uint32_t max_batch_reads; /* reads per batch (slot capacity) */
+    uint64_t max_batch_bytes; /* read bytes per batch (slot capacity) */
+    uint32_t policy;          /* RAMBO_SERVE_* */
+    uint32_t queue_cap;       /* pending reads before submit returns RAMBO_EBUSY */
+} rambo_server_config_t;
+
+typedef struct {
+    uint64_t tag;         /* as submitted */
+    double t_arrival;     /* as submitted (rambo_clock() seconds) */
+    double t_admit;       /* its batch was formed */
+    double t_done;        /* its result reached host memory */
+    int32_t status;       /* RAMBO_OK */
+    uint32_t batch_reads; /* reads in the batch it ran in */
+} rambo_completion_t;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, batches;
+    uint64_t max_batch_reads, max_inflight_bytes, backpressure_waits;
+    uint64_t pending, inflight_bytes;
+} rambo_server_stats_t;
+
+/* Monotonic clock (seconds) the server stamps times with. */
+double rambo_clock(void);
+
+/* Start a server on index h (which must stay alive and receive no other work
+ * until rambo_server_stop). Allocates the slots' pinned staging buffers,
+ * device buffers and graphs, and starts a dispatcher and a completion
+ * thread. NULL on error. */
+rambo_server_t *rambo_server_start(rambo_t *h, const rambo_server_config_t *cfg);
+
+/* Queue one read (host bytes, copied). t_arrival is the caller's arrival
+ * time on rambo_clock(). RAMBO_EBUSY if queue_cap reads are pending,
+ * RAMBO_EINVAL if the read can never fit a batch or the budget. */
+int rambo_server_submit(rambo_server_t *s, const uint8_t *read, uint64_t len, uint64_t tag, double t_arrival);
+
+/* Open-loop replay: copy n reads (host arrays as in rambo_query_seqs) and
+ * submit read i, with tag tag0 + i, at time t_arrival[i] on rambo_clock()
+ * from a feeder thread. Returns at once. */
+int rambo_server_submit_schedule(rambo_server_t *s, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
+                                 const double *t_arrival, uint64_t tag0);
+
+/* Take up to max completions (and, if results is not NULL, their W-word
+ * bitsets into results[k*W ..]), waiting up to timeout_s for the first.
+ * Returns the number taken, or a negative status if the server failed. */
+int rambo_server_poll(rambo_server_t *s, rambo_completion_t *out, uint64_t *results, uint32_t max,
+                      double timeout_s);
+
+int rambo_server_stats(rambo_server_t *s, rambo_server_stats_t *out);
+
+/* Stop the feeder, finish every queued and in-flight read, join the threads
+ * and free the server. Completions not yet polled are discarded. */
+int rambo_server_stop(rambo_server_t *s);
+
 #ifdef __cplusplus
 }
 #endif

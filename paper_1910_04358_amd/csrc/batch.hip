@@ -161,22 +161,31 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
                 __builtin_amdgcn_wave_barrier();
                 continue;
             }
+            // Publish this tile's masks, then count the tile done. Both are
+            // agent-scope atomic read-modify-writes, performed at the point
+            // of coherence of all XCDs; the workgroup-scope fence between them
+            // makes the wave wait for the ANDs to complete before it counts
+            // (no L2 write-back is needed: nothing here is a plain store).
             if (!skip && lane < (uint32_t)G) {
 #pragma unroll
                 for (int r = 0; r < MAXR; r++)
                     if (r < (int)ix.R)
 #pragma unroll
                         for (int s = 0; s < SEG; s++)
-                            if (acc[r].w[s] != 0xFFFFFFFFu) atomicAnd(rm + r * ix.RW + lane * SEG + s, acc[r].w[s]);
+                            if (acc[r].w[s] != 0xFFFFFFFFu)
+                                __hip_atomic_fetch_and(rm + r * ix.RW + lane * SEG + s, acc[r].w[s], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
             }
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             uint32_t prev = 0;
-            if (lane == 0) prev = atomicAdd(bb.done + i, 1u);
+            if (lane == 0) prev = __hip_atomic_fetch_add(bb.done + i, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             prev = __shfl(prev, 0);
             if (prev + 1 == ntiles) {
-                // last tile of read i: every other tile's AND is visible
-                __threadfence();
-                for (uint32_t w = lane; w < mw; w += 64) M[w] = load_coherent(rm + w);
+                // last tile of read i: every other tile's ANDs were performed
+                // before its count; read the masks with atomic RMWs as well
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                for (uint32_t w = lane; w < mw; w += 64)
+                    M[w] = __hip_atomic_fetch_or(rm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 if (lds_some_rep_empty(ix, M, lane)) write_zeros(o, ix.W, lane);

@@ -228,48 +228,69 @@ __device__ __forceinline__ void probe_rep(const Index &ix, uint64_t x, uint32_t 
     }
 }
 
-// One step of 64 windows, repetition by repetition: every valid window's
-// term is probed in repetition r, the masks of the step's terms are ANDed
-// across the wave (G lanes share a term) into the read's running mask
-// acc[r]. With early exit, the step stops at the first repetition whose
-// running mask is empty: the read's answer is then empty whatever the other
-// repetitions hold (Section 3.3.1). Returns the number of repetitions
-// probed; *dead tells whether the read ended.
+// Probe one term in repetition r into cm (the lanes of a term group split the
+// row); for G > 1 the group's term is fetched from the lane that extracted it.
+template <int SEG, int G>
+__device__ __forceinline__ void probe_rep_step(const Index &ix, const Window &wv, bool valid, uint32_t lane, int r,
+                                               Seg<SEG> &cm) {
+#pragma unroll
+    for (int s = 0; s < SEG; s++) cm.w[s] = 0xFFFFFFFFu;
+    if constexpr (G == 1) {
+        if (valid) probe_rep<SEG>(ix, wv.canon, 0, r, cm);
+    } else {
+        constexpr int KPW = 64 / G;
+#pragma unroll 1
+        for (int sub = 0; sub < G; sub++) {
+            const int src = sub * KPW + (int)(lane / G);
+            const uint64_t x = __shfl(wv.canon, src);
+            const int v = __shfl((int)valid, src);
+            if (v) probe_rep<SEG>(ix, x, lane % G, r, cm);
+        }
+    }
+}
+
+// AND a repetition's step mask across the wave into the running mask;
+// returns whether the running mask is still non-empty.
+template <int SEG, int G>
+__device__ __forceinline__ bool fold_rep(const Seg<SEG> &cm, Seg<SEG> &acc) {
+    const uint64_t group0 = (G >= 64) ? ~0ULL : ((1ULL << G) - 1);
+    uint32_t o = 0;
+#pragma unroll
+    for (int s = 0; s < SEG; s++) {
+        acc.w[s] &= and_across_groups<G>(cm.w[s]);
+        o |= acc.w[s];
+    }
+    if constexpr (G == 1) return o != 0;  // uniform already
+    else return (__ballot(o != 0) & group0) != 0;
+}
+
+// One step of 64 windows: repetition 0 first, then the other repetitions
+// together (their loads all in flight at once). The step's masks are ANDed
+// across the wave (G lanes share a term) into the read's running masks acc.
+// With early exit the step stops once a running mask is empty -- the read's
+// answer is then empty whatever the other repetitions hold (Section 3.3.1);
+// random and erroneous reads mostly end at repetition 0 of their first
+// step. Returns the number of repetitions probed; *dead tells whether the
+// read ended.
 template <int SEG, int G>
 __device__ __forceinline__ uint32_t probe_step(const Index &ix, const Window &wv, bool valid, uint32_t lane,
                                                Seg<SEG> (&acc)[MAXR], bool early_exit, bool *dead) {
-    const uint64_t group0 = (G >= 64) ? ~0ULL : ((1ULL << G) - 1);
     *dead = false;
-#pragma unroll
-    for (int r = 0; r < MAXR; r++) {
-        if (r < (int)ix.R) {
-            Seg<SEG> cm;
-#pragma unroll
-            for (int s = 0; s < SEG; s++) cm.w[s] = 0xFFFFFFFFu;
-            if constexpr (G == 1) {
-                if (valid) probe_rep<SEG>(ix, wv.canon, 0, r, cm);
-            } else {
-                constexpr int KPW = 64 / G;
-#pragma unroll 1
-                for (int sub = 0; sub < G; sub++) {
-                    const int src = sub * KPW + (int)(lane / G);
-                    const uint64_t x = __shfl(wv.canon, src);
-                    const int v = __shfl((int)valid, src);
-                    if (v) probe_rep<SEG>(ix, x, lane % G, r, cm);
-                }
-            }
-            uint32_t o = 0;
-#pragma unroll
-            for (int s = 0; s < SEG; s++) {
-                acc[r].w[s] &= and_across_groups<G>(cm.w[s]);
-                o |= acc[r].w[s];
-            }
-            if (early_exit && (__ballot(o != 0) & group0) == 0) {
-                *dead = true;
-                return (uint32_t)r + 1;
-            }
-        }
+    Seg<SEG> cm0;
+    probe_rep_step<SEG, G>(ix, wv, valid, lane, 0, cm0);
+    if (!fold_rep<SEG, G>(cm0, acc[0]) && early_exit) {
+        *dead = true;
+        return 1;
     }
+    Seg<SEG> cm[MAXR];
+#pragma unroll
+    for (int r = 1; r < MAXR; r++)
+        if (r < (int)ix.R) probe_rep_step<SEG, G>(ix, wv, valid, lane, r, cm[r]);
+    bool alive = true;
+#pragma unroll
+    for (int r = 1; r < MAXR; r++)
+        if (r < (int)ix.R) alive &= fold_rep<SEG, G>(cm[r], acc[r]);
+    *dead = early_exit && !alive;
     return ix.R;
 }
 

@@ -1,0 +1,427 @@
+// Serving loop: continuous batching of arriving reads against a resident
+// index.
+//
+// Requests wait in a host queue. A dispatcher thread forms a batch from
+// everything pending that fits a free staging slot and the admission budget
+// (device bytes of the in-flight reads and their result state), copies it
+// to the slot's device buffers on the slot's own stream and replays the
+// slot's captured batched-query graphs; up to `slots` batches are in flight
+// at once, so the copies of one batch overlap the kernels of another and
+// reads that arrive while others run join the next batch. A completion
+// thread waits for each batch in order, copies its results back and stamps
+// the completion time. Each result is the same bitset rambo_query_seqs gives
+// for that read alone: reads are independent within a batch.
+//
+// The serial policy is the one-batch-at-a-time baseline: take everything
+// that has arrived, run the plain kernel, wait, repeat.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+
+#include "batch.h"
+
+namespace rambo {
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    const uint8_t *bytes;  // into owned storage
+    uint64_t len;
+    uint64_t tag;
+    double t_arrival;
+    std::shared_ptr<std::vector<uint8_t>> own;  // single submissions own their bytes
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint8_t *h_seqs = nullptr, *d_seqs = nullptr;
+    uint64_t *h_offs = nullptr, *d_offs = nullptr;
+    uint64_t *h_out = nullptr, *d_out = nullptr;
+    uint64_t *h_n = nullptr;
+    std::shared_ptr<BatchGraph> small, large;  // graphs for small and full batches
+    std::vector<Request> reqs;
+    uint64_t budget = 0;
+    double t_admit = 0;
+};
+
+}  // namespace rambo
+
+struct rambo_server_s {
+    rambo_s *h = nullptr;
+    rambo_server_config_t cfg{};
+    std::vector<rambo::Slot> slots;
+    std::mutex mu;  // pending queue, free slots, budget, stats
+    std::condition_variable cv_dispatch, cv_done, cv_poll;
+    std::deque<rambo::Request> pending;
+    std::deque<int> free_slots, inflight;
+    uint64_t budget_used = 0;
+    bool stopping = false;
+    int error = RAMBO_OK;
+    std::string error_msg;
+    std::thread dispatcher, completer, feeder;
+    // completions
+    std::mutex cmu;
+    std::deque<rambo_completion_t> comp;
+    std::deque<std::vector<uint64_t>> comp_bits;
+    // scheduled submissions
+    std::vector<uint8_t> sched_bytes;
+    std::vector<uint64_t> sched_offs;
+    std::vector<double> sched_t;
+    uint64_t sched_tag0 = 0;
+    std::atomic<bool> feeder_stop{false};
+    rambo_server_stats_t stats{};
+};
+
+namespace rambo {
+
+static uint64_t request_cost(const rambo_s *h, uint64_t len) {
+    // read bytes, its offset, its result bitset, its running masks
+    return len + 8 + h->W * 8 + (uint64_t)h->R * h->RW * 4 + 16;
+}
+
+static void server_fail(rambo_server_s *s, int st) {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->error == RAMBO_OK) {
+        s->error = st;
+        s->error_msg = rambo_last_error();
+    }
+    s->stopping = true;
+    s->cv_dispatch.notify_all();
+    s->cv_done.notify_all();
+    s->cv_poll.notify_all();
+}
+
+static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n, uint64_t bytes) {
+    rambo_s *h = s->h;
+    HIP_CHECK(hipMemcpyAsync(sl.d_seqs, sl.h_seqs, bytes ? bytes : 1, hipMemcpyHostToDevice, sl.stream));
+    HIP_CHECK(hipMemcpyAsync(sl.d_offs, sl.h_offs, (n + 1) * 8, hipMemcpyHostToDevice, sl.stream));
+    int st;
+    if (s->cfg.policy == RAMBO_SERVE_SERIAL) {
+        st = launch_query_seqs_plain(h, sl.d_seqs, sl.d_offs, n, sl.d_out, sl.stream, default_seg(h->RW));
+    } else {
+        BatchGraph &bg = (n <= sl.small->cap) ? *sl.small : *sl.large;
+        *sl.h_n = n;
+        HIP_CHECK(hipMemcpyAsync(bg.d_n, sl.h_n, 8, hipMemcpyHostToDevice, sl.stream));
+        st = launch_batch_graph(h, bg, sl.stream);
+    }
+    if (st != RAMBO_OK) return st;
+    HIP_CHECK(hipMemcpyAsync(sl.h_out, sl.d_out, n * h->W * 8, hipMemcpyDeviceToHost, sl.stream));
+    HIP_CHECK(hipEventRecord(sl.done, sl.stream));
+    return RAMBO_OK;
+}
+
+static void dispatcher_main(rambo_server_s *s) {
+    (void)hipSetDevice(s->h->device);
+    const uint64_t W = s->h->W;
+    (void)W;
+    for (;;) {
+        int slot = -1;
+        uint64_t n = 0, bytes = 0, cost = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_dispatch.wait(lk, [&] {
+                return s->stopping || (!s->pending.empty() && !s->free_slots.empty() &&
+                                       s->budget_used + request_cost(s->h, s->pending.front().len) <= s->cfg.budget_bytes);
+            });
+            if (s->stopping && (s->pending.empty() || s->error != RAMBO_OK)) return;
+            if (s->pending.empty() || s->free_slots.empty()) continue;
+            slot = s->free_slots.front();
+            s->free_slots.pop_front();
+            Slot &sl = s->slots[slot];
+            sl.reqs.clear();
+            // everything that has arrived and fits the slot and the budget
+            while (!s->pending.empty() && n < s->cfg.max_batch_reads) {
+                const Request &r = s->pending.front();
+                const uint64_t c = request_cost(s->h, r.len);
+                if (bytes + r.len > s->cfg.max_batch_bytes) break;
+                if (s->budget_used + cost + c > s->cfg.budget_bytes) {
+                    s->stats.backpressure_waits++;
+                    break;
+                }
+                sl.reqs.push_back(r);
+                s->pending.pop_front();
+                bytes += r.len;
+                cost += c;
+                n++;
+            }
+            s->budget_used += cost;
+            if (s->budget_used > s->stats.max_inflight_bytes) s->stats.max_inflight_bytes = s->budget_used;
+            s->stats.batches++;
+            if (n > s->stats.max_batch_reads) s->stats.max_batch_reads = n;
+        }
+        Slot &sl = s->slots[slot];
+        sl.budget = cost;
+        sl.t_admit = now_s();
+        uint64_t off = 0;
+        sl.h_offs[0] = 0;
+        for (uint64_t i = 0; i < n; i++) {
+            memcpy(sl.h_seqs + off, sl.reqs[i].bytes, sl.reqs[i].len);
+            off += sl.reqs[i].len;
+            sl.h_offs[i + 1] = off;
+        }
+        int st = launch_slot(s, sl, n, bytes);
+        if (st != RAMBO_OK) {
+            server_fail(s, st);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->inflight.push_back(slot);
+        }
+        s->cv_done.notify_one();
+        if (s->cfg.policy == RAMBO_SERVE_SERIAL) {
+            // one batch at a time: wait until the completion thread has freed it
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_dispatch.wait(lk, [&] { return s->stopping || s->inflight.empty(); });
+        }
+    }
+}
+
+static void completer_main(rambo_server_s *s) {
+    (void)hipSetDevice(s->h->device);
+    const uint64_t W = s->h->W;
+    for (;;) {
+        int slot;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_done.wait(lk, [&] { return !s->inflight.empty() || (s->stopping && s->pending.empty()) || s->error; });
+            if (s->inflight.empty()) {
+                if (s->stopping) return;
+                continue;
+            }
+            slot = s->inflight.front();
+        }
+        Slot &sl = s->slots[slot];
+        // spin on the event: completion latency matters more than one host core
+        hipError_t e;
+        while ((e = hipEventQuery(sl.done)) == hipErrorNotReady) std::this_thread::yield();
+        if (e != hipSuccess) {
+            fail(RAMBO_EDEVICE, "server: batch failed: %s", hipGetErrorString(e));
+            server_fail(s, RAMBO_EDEVICE);
+            return;
+        }
+        const double t_done = now_s();
+        {
+            std::lock_guard<std::mutex> g(s->cmu);
+            for (size_t i = 0; i < sl.reqs.size(); i++) {
+                rambo_completion_t c;
+                c.tag = sl.reqs[i].tag;
+                c.t_arrival = sl.reqs[i].t_arrival;
+                c.t_admit = sl.t_admit;
+                c.t_done = t_done;
+                c.status = RAMBO_OK;
+                c.batch_reads = (uint32_t)sl.reqs.size();
+                s->comp.push_back(c);
+                s->comp_bits.emplace_back(sl.h_out + i * W, sl.h_out + (i + 1) * W);
+            }
+        }
+        s->cv_poll.notify_all();
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->inflight.pop_front();
+            s->budget_used -= sl.budget;
+            s->stats.completed += sl.reqs.size();
+            sl.reqs.clear();
+            s->free_slots.push_back(slot);
+        }
+        s->cv_dispatch.notify_all();
+    }
+}
+
+static int enqueue_request(rambo_server_s *s, Request r) {
+    if (r.len > s->cfg.max_batch_bytes || request_cost(s->h, r.len) > s->cfg.budget_bytes)
+        return fail(RAMBO_EINVAL, "server: read of %llu bytes exceeds the batch or budget capacity",
+                    (unsigned long long)r.len);
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->error != RAMBO_OK) return fail(s->error, "server stopped: %s", s->error_msg.c_str());
+        if (s->stopping) return fail(RAMBO_EINVAL, "server is stopping");
+        if (s->pending.size() >= s->cfg.queue_cap) {
+            s->stats.rejected++;
+            return fail(RAMBO_EBUSY, "server queue full (%u pending)", s->cfg.queue_cap);
+        }
+        s->pending.push_back(std::move(r));
+        s->stats.submitted++;
+    }
+    s->cv_dispatch.notify_one();
+    return RAMBO_OK;
+}
+
+static void feeder_main(rambo_server_s *s) {
+    const uint64_t n = s->sched_t.size();
+    for (uint64_t i = 0; i < n && !s->feeder_stop.load(); i++) {
+        const double t = s->sched_t[i];
+        for (;;) {
+            const double d = t - now_s();
+            if (d <= 0) break;
+            if (d > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(d - 1e-4));
+            else std::this_thread::yield();
+        }
+        Request r{s->sched_bytes.data() + s->sched_offs[i], s->sched_offs[i + 1] - s->sched_offs[i], s->sched_tag0 + i, t,
+                  nullptr};
+        // open loop: a full queue drops nothing here, the feeder waits for room
+        while (!s->feeder_stop.load()) {
+            int st = enqueue_request(s, r);
+            if (st == RAMBO_OK) break;
+            if (st != RAMBO_EBUSY) return;
+            std::this_thread::yield();
+        }
+    }
+}
+
+static void free_slot(Slot &sl) {
+    sl.small.reset();
+    sl.large.reset();
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.h_seqs) (void)hipHostFree(sl.h_seqs);
+    if (sl.h_offs) (void)hipHostFree(sl.h_offs);
+    if (sl.h_out) (void)hipHostFree(sl.h_out);
+    if (sl.h_n) (void)hipHostFree(sl.h_n);
+    if (sl.d_seqs) (void)hipFree(sl.d_seqs);
+    if (sl.d_offs) (void)hipFree(sl.d_offs);
+    if (sl.d_out) (void)hipFree(sl.d_out);
+}
+
+static int setup_slot(rambo_server_s *s, Slot &sl) {
+    rambo_s *h = s->h;
+    const uint64_t R = s->cfg.max_batch_reads, BY = s->cfg.max_batch_bytes;
+    HIP_CHECK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    HIP_CHECK(hipHostMalloc((void **)&sl.h_seqs, BY, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void **)&sl.h_offs, (R + 1) * 8, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void **)&sl.h_out, R * h->W * 8, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void **)&sl.h_n, 8, hipHostMallocDefault));
+    HIP_CHECK(hipMalloc(&sl.d_seqs, BY));
+    HIP_CHECK(hipMalloc(&sl.d_offs, (R + 1) * 8));
+    HIP_CHECK(hipMalloc(&sl.d_out, R * h->W * 8));
+    if (s->cfg.policy == RAMBO_SERVE_CONTINUOUS) {
+        Tune large = h->tune;
+        if (!h->tuned) large.seg = default_seg(h->RW);
+        // small batches: a grid of about one wave per read
+        Tune small = large;
+        small.waves_per_cu = std::max(small.wpb, 2);
+        const uint64_t small_cap = std::min<uint64_t>(R, (uint64_t)h->n_cu * 2);
+        int st = make_batch_graph(h, small, sl.d_seqs, sl.d_offs, small_cap, sl.d_out, nullptr, sl.small);
+        if (st == RAMBO_OK) st = make_batch_graph(h, large, sl.d_seqs, sl.d_offs, R, sl.d_out, nullptr, sl.large);
+        if (st != RAMBO_OK) return st;
+    }
+    return RAMBO_OK;
+}
+
+}  // namespace rambo
+
+using namespace rambo;
+
+RAMBO_API double rambo_clock(void) { return now_s(); }
+
+RAMBO_API rambo_server_t *rambo_server_start(rambo_t *h, const rambo_server_config_t *cfg) {
+    if (!h || !cfg || cfg->slots == 0 || cfg->slots > 64 || cfg->max_batch_reads == 0 || cfg->max_batch_bytes == 0 ||
+        cfg->budget_bytes == 0 || cfg->queue_cap == 0 ||
+        (cfg->policy != RAMBO_SERVE_CONTINUOUS && cfg->policy != RAMBO_SERVE_SERIAL)) {
+        fail(RAMBO_EINVAL, "rambo_server_start: bad configuration");
+        return nullptr;
+    }
+    auto *s = new rambo_server_s();
+    s->h = h;
+    s->cfg = *cfg;
+    const uint32_t nslots = cfg->policy == RAMBO_SERVE_SERIAL ? 1 : cfg->slots;
+    s->slots.resize(nslots);
+    int st = RAMBO_OK;
+    for (uint32_t i = 0; i < nslots && st == RAMBO_OK; i++) {
+        st = setup_slot(s, s->slots[i]);
+        s->free_slots.push_back((int)i);
+    }
+    if (st != RAMBO_OK) {
+        for (auto &sl : s->slots) free_slot(sl);
+        delete s;
+        return nullptr;
+    }
+    s->dispatcher = std::thread(dispatcher_main, s);
+    s->completer = std::thread(completer_main, s);
+    return s;
+}
+
+RAMBO_API int rambo_server_submit(rambo_server_t *s, const uint8_t *read, uint64_t len, uint64_t tag, double t_arrival) {
+    if (!s || (!read && len)) return fail(RAMBO_EINVAL, "rambo_server_submit: bad argument");
+    auto own = std::make_shared<std::vector<uint8_t>>(read, read + len);
+    Request r{own->data(), len, tag, t_arrival, own};
+    return enqueue_request(s, r);
+}
+
+RAMBO_API int rambo_server_submit_schedule(rambo_server_t *s, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
+                                           const double *t_arrival, uint64_t tag0) {
+    if (!s || !offsets || !t_arrival || (n && !seqs)) return fail(RAMBO_EINVAL, "rambo_server_submit_schedule: bad argument");
+    if (s->feeder.joinable()) return fail(RAMBO_EBUSY, "rambo_server_submit_schedule: a schedule is already running");
+    for (uint64_t i = 0; i < n; i++)
+        if (offsets[i + 1] < offsets[i]) return fail(RAMBO_EINVAL, "rambo_server_submit_schedule: offsets decrease");
+    s->sched_bytes.assign(seqs, seqs + (n ? offsets[n] - offsets[0] : 0));
+    s->sched_offs.resize(n + 1);
+    for (uint64_t i = 0; i <= n; i++) s->sched_offs[i] = offsets[i] - offsets[0];
+    s->sched_t.assign(t_arrival, t_arrival + n);
+    s->sched_tag0 = tag0;
+    s->feeder_stop = false;
+    s->feeder = std::thread(feeder_main, s);
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_server_poll(rambo_server_t *s, rambo_completion_t *out, uint64_t *results, uint32_t max,
+                                double timeout_s) {
+    if (!s || (!out && max)) return fail(RAMBO_EINVAL, "rambo_server_poll: bad argument");
+    const uint64_t W = s->h->W;
+    std::unique_lock<std::mutex> lk(s->cmu);
+    if (s->comp.empty() && timeout_s > 0) {
+        s->cv_poll.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return !s->comp.empty() || s->error; });
+    }
+    uint32_t k = 0;
+    while (k < max && !s->comp.empty()) {
+        out[k] = s->comp.front();
+        if (results) memcpy(results + (uint64_t)k * W, s->comp_bits.front().data(), W * 8);
+        s->comp.pop_front();
+        s->comp_bits.pop_front();
+        k++;
+    }
+    if (k == 0 && s->error != RAMBO_OK) return fail(s->error, "server failed: %s", s->error_msg.c_str());
+    return (int)k;
+}
+
+RAMBO_API int rambo_server_stats(rambo_server_t *s, rambo_server_stats_t *out) {
+    if (!s || !out) return fail(RAMBO_EINVAL, "rambo_server_stats: bad argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    out->pending = s->pending.size();
+    out->inflight_bytes = s->budget_used;
+    return RAMBO_OK;
+}
+
+RAMBO_API int rambo_server_stop(rambo_server_t *s) {
+    if (!s) return RAMBO_OK;
+    s->feeder_stop = true;
+    if (s->feeder.joinable()) s->feeder.join();
+    {
+        // drain: let pending and in-flight batches finish
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_dispatch.notify_all();
+        s->cv_dispatch.wait_for(lk, std::chrono::seconds(60),
+                                [&] { return s->error || (s->pending.empty() && s->inflight.empty()); });
+        s->stopping = true;
+    }
+    s->cv_dispatch.notify_all();
+    s->cv_done.notify_all();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    if (s->completer.joinable()) s->completer.join();
+    int st = s->error;
+    for (auto &sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        free_slot(sl);
+    }
+    if (st != RAMBO_OK) fail(st, "server failed: %s", s->error_msg.c_str());
+    delete s;
+    return st;
+}

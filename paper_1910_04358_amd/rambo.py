@@ -64,7 +64,31 @@ SIGNATURES = {
     "rambo_get_tune": ([_vp, ctypes.POINTER(TuneC)], _i32),
     "rambo_set_tune": ([_vp, ctypes.POINTER(TuneC)], _i32),
     "rambo_last_batch_ms": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], _i32),
+    "rambo_clock": ([], ctypes.c_double),
+    "rambo_server_start": ([_vp, _vp], _vp),
+    "rambo_server_submit": ([_vp, _vp, _u64, _u64, ctypes.c_double], _i32),
+    "rambo_server_submit_schedule": ([_vp, _vp, _vp, _u64, _vp, _u64], _i32),
+    "rambo_server_poll": ([_vp, _vp, _vp, _u32, ctypes.c_double], _i32),
+    "rambo_server_stats": ([_vp, _vp], _i32),
+    "rambo_server_stop": ([_vp], _i32),
 }
+
+SERVE_CONTINUOUS, SERVE_SERIAL = 0, 1
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", _u64), ("slots", _u32), ("max_batch_reads", _u32), ("max_batch_bytes", _u64),
+                ("policy", _u32), ("queue_cap", _u32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", _u64), ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("status", ctypes.c_int32), ("batch_reads", _u32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, _u64) for n in ("submitted", "completed", "rejected", "batches", "max_batch_reads",
+                                     "max_inflight_bytes", "backpressure_waits", "pending", "inflight_bytes")]
 
 
 class RamboError(RuntimeError):
@@ -309,6 +333,58 @@ class Rambo:
     def set_tune(self, tune: Tune) -> None:
         t = TuneC(tune.seg, tune.tile, tune.waves_per_cu, tune.wpb, tune.grab, 1)
         _check(lib().rambo_set_tune(self._h, ctypes.byref(t)))
+
+
+def clock() -> float:
+    return lib().rambo_clock()
+
+
+class Server:
+    """Continuous-batching server over a resident index (RAMBO_SERVE_*)."""
+
+    def __init__(self, idx: "Rambo", budget_bytes=4 << 30, slots=4, max_batch_reads=8192,
+                 max_batch_bytes=8 << 20, policy=SERVE_CONTINUOUS, queue_cap=1 << 20):
+        self.idx = idx
+        cfg = ServerConfig(budget_bytes, slots, max_batch_reads, max_batch_bytes, policy, queue_cap)
+        self._s = lib().rambo_server_start(idx._h, ctypes.byref(cfg))
+        if not self._s:
+            raise RamboError(lib().rambo_last_status(), lib().rambo_last_error().decode(errors="replace"))
+        self._keep = []
+
+    def submit(self, read: bytes, tag: int, t_arrival: float | None = None) -> int:
+        t = clock() if t_arrival is None else t_arrival
+        return lib().rambo_server_submit(self._s, read, len(read), tag, t)
+
+    def submit_schedule(self, seqs: np.ndarray, offsets: np.ndarray, t_arrival: np.ndarray, tag0: int = 0):
+        seqs = np.ascontiguousarray(seqs, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        t = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        _check(lib().rambo_server_submit_schedule(self._s, ctypes.c_void_p(seqs.ctypes.data),
+                                                  ctypes.c_void_p(offsets.ctypes.data), offsets.size - 1,
+                                                  ctypes.c_void_p(t.ctypes.data), tag0))
+
+    def poll(self, max_n=4096, timeout_s=0.05, results=True):
+        comp = (Completion * max_n)()
+        res = np.zeros((max_n, self.idx.W), dtype=np.uint64) if results else None
+        k = _check(lib().rambo_server_poll(self._s, comp, ctypes.c_void_p(res.ctypes.data) if results else None,
+                                           max_n, timeout_s))
+        return comp[:k], (res[:k] if results else None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().rambo_server_stats(self._s, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_s", None):
+            s, self._s = self._s, None
+            _check(lib().rambo_server_stop(s))
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
 
 
 def check_offsets(offsets, nbytes: int) -> None:

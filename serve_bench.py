@@ -1,0 +1,83 @@
+"""Served (continuous batching) measurement on a resident index: open-loop
+Poisson arrivals at several rates, p50/p99 latency from the *scheduled*
+arrival time to the result in host memory, throughput, and the one-batch-at-
+a-time plain baseline on the same arrivals. Every served result is checked
+bit for bit against the plain kernel run on the whole set of reads.
+
+Used by bench.py (run(idx, workload, device, log)).
+"""
+from __future__ import annotations
+
+from dataclasses import replace
+
+import numpy as np
+
+RATES = (1000, 5000, 10000, 25000, 50000)
+
+
+def _serve(idx, reads, arrivals, policy, budget, slots=4, max_batch_reads=8192, max_batch_bytes=8 << 20):
+    from paper_1910_04358_amd import Server, clock
+
+    n = reads.n
+    srv = Server(idx, budget_bytes=budget, slots=slots, max_batch_reads=max_batch_reads,
+                 max_batch_bytes=max_batch_bytes, policy=policy)
+    t0 = clock() + 0.05
+    sched = t0 + arrivals
+    srv.submit_schedule(reads.seqs, reads.offsets, sched)
+    done = np.zeros(n, dtype=bool)
+    t_done = np.zeros(n)
+    bits = np.zeros((n, idx.W), dtype=np.uint64)
+    got = 0
+    while got < n:
+        comp, res = srv.poll(max_n=8192, timeout_s=0.05)
+        for k, c in enumerate(comp):
+            i = c.tag
+            done[i] = True
+            t_done[i] = c.t_done
+            bits[i] = res[k]
+        got += len(comp)
+        if len(comp) == 0 and clock() > sched[-1] + 60:
+            raise RuntimeError("server stalled")
+    stats = srv.stats()
+    srv.stop()
+    lat = t_done - sched
+    keep = np.argsort(sched)[int(0.05 * n):]  # the first 5 % of arrivals warm up
+    return {
+        "p50_ms": float(np.percentile(lat[keep], 50) * 1e3),
+        "p99_ms": float(np.percentile(lat[keep], 99) * 1e3),
+        "mean_ms": float(lat[keep].mean() * 1e3),
+        "throughput_reads_per_s": n / (t_done.max() - sched[0]),
+        "batches": int(stats["batches"]),
+        "max_batch_reads": int(stats["max_batch_reads"]),
+        "max_inflight_bytes": int(stats["max_inflight_bytes"]),
+    }, bits
+
+
+def run(idx, w, dev, log, rates=RATES, seconds=2.0, min_reads=2000, max_reads=100_000, budget=4 << 30):
+    import gen
+    from paper_1910_04358_amd import MODE_PLAIN, SERVE_CONTINUOUS, SERVE_SERIAL
+    import torch
+
+    out = {"rates": [], "budget_bytes": budget, "seconds_per_rate": seconds,
+           "note": "latency = result in host memory minus scheduled arrival; first 5% discarded"}
+    mode = MODE_PLAIN
+    idx.set_mode(mode)
+    for k, lam in enumerate(rates):
+        n = int(min(max_reads, max(min_reads, lam * seconds)))
+        rm = replace(w.reads, qseed=w.reads.qseed + 10 + k)
+        reads = gen.reads(w.docs, rm, n)
+        arrivals = gen.poisson_arrivals(4000 + k, float(lam), n)
+        seqs = torch.from_numpy(reads.seqs).to(dev)
+        offs = torch.from_numpy(reads.offsets.view(np.int64)).to(dev)
+        ref = idx.query_seqs(seqs, offs).cpu().numpy().view(np.uint64)
+        rec = {"rate": lam, "reads": n}
+        for name, policy in (("served", SERVE_CONTINUOUS), ("serial_plain", SERVE_SERIAL)):
+            m, bits = _serve(idx, reads, arrivals, policy, budget)
+            if not np.array_equal(bits, ref):
+                raise SystemExit("served results differ from the plain kernel at rate %d (%s)" % (lam, name))
+            rec[name] = m
+        log("serve %6d reads/s: served p50 %.3f p99 %.3f ms | serial p50 %.3f p99 %.3f ms"
+            % (lam, rec["served"]["p50_ms"], rec["served"]["p99_ms"], rec["serial_plain"]["p50_ms"],
+               rec["serial_plain"]["p99_ms"]))
+        out["rates"].append(rec)
+    return out
