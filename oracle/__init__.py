@@ -59,6 +59,7 @@ def lib():
             "orc_bfu_insert_seq": ([vp, u32, vp, vp, u64], None),
             "orc_bfu_test_seq": ([vp, u32, vp, vp, u64], i32),
             "orc_popcount_bfu": ([vp, u32, u32], u64),
+            "orc_bfu_test_seqs": ([vp, u32, vp, vp, vp, u64, vp, i32], None),
             "orc_query_kmer_def": ([vp, u64, vp], None),
             "orc_query_kmer_alg2": ([vp, u64, vp], None),
             "orc_query_seq_def": ([vp, vp, u64, vp], None),
@@ -176,6 +177,15 @@ class Oracle:
         s = np.frombuffer(bytes(seq), dtype=np.uint8) if not isinstance(seq, np.ndarray) else seq
         s = np.ascontiguousarray(s, dtype=np.uint8)
         return bool(lib().orc_bfu_test_seq(self._h, r, _p(f), _p(s), s.size))
+
+    def bfu_test_seqs(self, r: int, f: np.ndarray, seqs: np.ndarray, offsets: np.ndarray, nthreads=None):
+        """For every read: 1 iff each of its terms passes filter f of repetition r."""
+        seqs = np.ascontiguousarray(seqs, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n = offsets.size - 1
+        out = np.zeros(n, dtype=np.uint8)
+        lib().orc_bfu_test_seqs(self._h, r, _p(f), _p(seqs), _p(offsets), n, _p(out), nthreads or _nthreads())
+        return out.astype(bool)
 
     # -- queries
     def query_kmer(self, x: int, mode=MODE_DEF) -> np.ndarray:

@@ -284,6 +284,15 @@ int orc_bfu_test_seq(const orc_t *o, uint32_t r, const uint64_t *f, const uint8_
     return 1;
 }
 
+/* orc_bfu_test_seq for n reads (seqs[offsets[i] .. offsets[i+1])) into
+ * out[i], parallel over reads. */
+void orc_bfu_test_seqs(const orc_t *o, uint32_t r, const uint64_t *f, const uint8_t *seqs, const uint64_t *offsets,
+                       uint64_t n, uint8_t *out, int nthreads) {
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; i++)
+        out[i] = (uint8_t)orc_bfu_test_seq(o, r, f, seqs + offsets[i], offsets[i + 1] - offsets[i]);
+}
+
 uint64_t orc_popcount_bfu(const orc_t *o, uint32_t r, uint32_t b) {
     uint64_t c = 0;
     const uint64_t *f = bfu(o, r, b);

@@ -15,16 +15,17 @@ struct BatchBufs {
     unsigned long long *head;  // queue position
 };
 
-// Two captured graphs for one set of buffers: prep (per-read tile counts
-// and their scan) and the persistent query kernel. The live batch size is
-// read from d_n on the device, so the graphs serve any n <= cap.
+// Captured graphs for one batch description: prep (per-read tile counts and
+// their scan; absent for the plain form) and the query kernel. The batch is
+// read from the device header `in`, so the graphs serve any batch of up to
+// cap reads placed anywhere the header points.
 struct BatchGraph {
     uint64_t cap = 0;
     unsigned blocks = 0;  // workgroups of the persistent launch
     Tune tune;
     BatchBufs bb{};
-    uint64_t *d_n = nullptr;
-    uint64_t *parts = nullptr;  // scan scratch
+    const InputHdr *in = nullptr;  // device
+    uint64_t *parts = nullptr;     // scan scratch
     void *mem = nullptr;
     hipGraph_t graph_prep = nullptr, graph_main = nullptr;
     hipGraphExec_t exec_prep = nullptr, exec_main = nullptr;
@@ -32,11 +33,14 @@ struct BatchGraph {
     ~BatchGraph();
 };
 
-// Capture the graphs for buffers (seqs, offs, out) of up to cap reads; if
-// n_value is given, the live size is set to it once.
-int make_batch_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t cap,
-                     uint64_t *out, const uint64_t *n_value, std::shared_ptr<BatchGraph> &res);
-// Enqueue both graphs on s with the timing events between them.
+// Persistent batched form for batches described by in_dev (device; or, if
+// null, by an owned header set once to *init), up to cap reads.
+int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const InputHdr *init, uint64_t cap,
+                     uint64_t *out, std::shared_ptr<BatchGraph> &res);
+// One-node graph of the plain kernel for batches described by in_dev.
+int make_plain_graph(rambo_s *h, const InputHdr *in_dev, uint64_t cap, uint64_t *out,
+                     std::shared_ptr<BatchGraph> &res);
+// Enqueue the graphs on s with the timing events between them.
 int launch_batch_graph(rambo_s *h, BatchGraph &bg, hipStream_t s);
 bool tune_valid(const rambo_s *h, const Tune &t);
 int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out, hipStream_t s);

@@ -28,9 +28,9 @@ __device__ __forceinline__ uint64_t n_windows(uint64_t beg, uint64_t end) {
     return end >= beg + 31 ? end - beg - 30 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_batch_prep(const uint64_t *__restrict__ offs, const uint64_t *n_ptr,
-                                                    uint32_t mw, uint32_t tile, BatchBufs bb) {
-    const uint64_t n = *n_ptr;
+__global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t mw, uint32_t tile, BatchBufs bb) {
+    const uint64_t n = in->n;
+    const uint64_t *__restrict__ offs = in->offs;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *bb.head = 0;
     if (i >= n) return;
@@ -85,10 +85,11 @@ __device__ __forceinline__ bool lds_some_rep_empty(const Index &ix, const uint32
 }
 
 template <int SEG, int G>
-__global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__restrict__ seqs,
-                                                    const uint64_t *__restrict__ offs, const uint64_t *n_ptr,
-                                                    uint64_t *__restrict__ out, BatchBufs bb, QueryOpts opt,
-                                                    int use_res, uint32_t tile, uint32_t grab) {
+__global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in, uint64_t *__restrict__ out,
+                                                    BatchBufs bb, QueryOpts opt, int use_res, uint32_t tile,
+                                                    uint32_t grab) {
+    const uint8_t *__restrict__ seqs = in->seqs;
+    const uint64_t *__restrict__ offs = in->offs;
     extern __shared__ uint64_t smem64[];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t mw = ix.R * ix.RW;
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
     uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * per_wave;
     uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + mwords) : nullptr;
 
-    const uint64_t n = *n_ptr;
+    const uint64_t n = in->n;
     const uint64_t total = n + bb.extra_off[n];
     uint64_t issued = 0;
     for (;;) {
@@ -200,16 +201,16 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const uint8_t *__r
 
 static constexpr uint32_t kMaxLds = 64 * 1024;
 
-static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint64_t *offs, hipStream_t s) {
+static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, hipStream_t s) {
     const uint32_t mw = h->R * h->RW;
-    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, offs, bg.d_n, mw,
+    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, bg.in, mw,
                        (uint32_t)tu.tile, bg.bb);
     HIP_CHECK(hipGetLastError());
-    return launch_exclusive_scan(bg.bb.extra, bg.d_n, bg.cap, bg.bb.extra_off, bg.parts, s);
+    // the header's first field is n
+    return launch_exclusive_scan(bg.bb.extra, &bg.in->n, bg.cap, bg.bb.extra_off, bg.parts, s);
 }
 
-static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_t *seqs, const uint64_t *offs,
-                        uint64_t *out, hipStream_t s) {
+static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *out, hipStream_t s) {
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
     const int G = (int)h->RW / tu.seg;
@@ -228,8 +229,8 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, const uint8_
         HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_batch_main<SEG, G>, 64 * tu.wpb, lds)); \
         const int per_cu = std::max(1, std::min(fit, tu.waves_per_cu / tu.wpb));                         \
         bg.blocks = (unsigned)(h->n_cu * per_cu);                                                          \
-        hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(bg.blocks), dim3(64 * tu.wpb), lds, s, ix, seqs, offs,  \
-                           bg.d_n, out, bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab);        \
+        hipLaunchKernelGGL((k_batch_main<SEG, G>), dim3(bg.blocks), dim3(64 * tu.wpb), lds, s, ix, bg.in, out,  \
+                           bg.bb, opt, use_res, (uint32_t)tu.tile, (uint32_t)tu.grab);                     \
     }
     RAMBO_DISPATCH_SPLIT(tu.seg, G)
 #undef RAMBO_SPLIT_BODY_
@@ -262,31 +263,63 @@ static int capture(rambo_s *h, hipGraph_t *g, hipGraphExec_t *exec, const std::f
     return RAMBO_OK;
 }
 
-int make_batch_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t cap,
-                     uint64_t *out, const uint64_t *n_value, std::shared_ptr<BatchGraph> &res) {
+// Graph state and, without an external header, an owned one set to *init.
+static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batch_bufs, const InputHdr *in_dev,
+                             const InputHdr *init) {
+    const size_t mw = (size_t)h->R * h->RW;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t b_mask = 0, b_done = 0, b_extra = 0, b_off = 0, b_parts = 0;
+    if (batch_bufs) {
+        b_mask = al(cap * mw * 4);
+        b_done = al(cap * 4);
+        b_extra = al(cap * 8);
+        b_off = al((cap + 1) * 8);
+        b_parts = al(scan_parts_needed(cap) * 8);
+    }
+    HIP_CHECK(hipMalloc(&bg.mem, b_mask + b_done + b_extra + b_off + b_parts + 512));
+    char *p = (char *)bg.mem;
+    bg.parts = (uint64_t *)p; p += b_parts;
+    bg.bb.rmask = (uint32_t *)p; p += b_mask;
+    bg.bb.done = (uint32_t *)p; p += b_done;
+    bg.bb.extra = (uint64_t *)p; p += b_extra;
+    bg.bb.extra_off = (uint64_t *)p; p += b_off;
+    bg.bb.head = (unsigned long long *)p; p += 256;
+    if (in_dev) {
+        bg.in = in_dev;
+    } else {
+        InputHdr *own = (InputHdr *)p;
+        HIP_CHECK(hipMemcpy(own, init, sizeof(InputHdr), hipMemcpyHostToDevice));
+        bg.in = own;
+    }
+    for (auto &e : bg.ev) HIP_CHECK(hipEventCreate(&e));
+    return RAMBO_OK;
+}
+
+int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const InputHdr *init, uint64_t cap,
+                     uint64_t *out, std::shared_ptr<BatchGraph> &res) {
     auto bg = std::make_shared<BatchGraph>();
     bg->cap = cap;
     bg->tune = tu;
-    const size_t mw = (size_t)h->R * h->RW;
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t b_mask = al(cap * mw * 4), b_done = al(cap * 4), b_extra = al(cap * 8), b_off = al((cap + 1) * 8);
-    const size_t b_parts = al(scan_parts_needed(cap) * 8);
-    HIP_CHECK(hipMalloc(&bg->mem, b_mask + b_done + b_extra + b_off + b_parts + 512));
-    char *p = (char *)bg->mem;
-    bg->parts = (uint64_t *)p; p += b_parts;
-    bg->bb.rmask = (uint32_t *)p; p += b_mask;
-    bg->bb.done = (uint32_t *)p; p += b_done;
-    bg->bb.extra = (uint64_t *)p; p += b_extra;
-    bg->bb.extra_off = (uint64_t *)p; p += b_off;
-    bg->bb.head = (unsigned long long *)p; p += 256;
-    bg->d_n = (uint64_t *)p;
-    if (n_value) HIP_CHECK(hipMemcpy(bg->d_n, n_value, 8, hipMemcpyHostToDevice));
-    for (auto &e : bg->ev) HIP_CHECK(hipEventCreate(&e));
-    int st = capture(h, &bg->graph_prep, &bg->exec_prep,
-                     [&](hipStream_t s) { return enqueue_prep(h, tu, *bg, offs, s); });
+    int st = alloc_graph_state(h, *bg, cap, true, in_dev, init);
+    if (st == RAMBO_OK)
+        st = capture(h, &bg->graph_prep, &bg->exec_prep, [&](hipStream_t s) { return enqueue_prep(h, tu, *bg, s); });
     if (st == RAMBO_OK)
         st = capture(h, &bg->graph_main, &bg->exec_main,
-                     [&](hipStream_t s) { return enqueue_main(h, tu, *bg, seqs, offs, out, s); });
+                     [&](hipStream_t s) { return enqueue_main(h, tu, *bg, out, s); });
+    if (st != RAMBO_OK) return st;
+    res = bg;
+    return RAMBO_OK;
+}
+
+int make_plain_graph(rambo_s *h, const InputHdr *in_dev, uint64_t cap, uint64_t *out,
+                     std::shared_ptr<BatchGraph> &res) {
+    auto bg = std::make_shared<BatchGraph>();
+    bg->cap = cap;
+    int st = alloc_graph_state(h, *bg, cap, false, in_dev, nullptr);
+    if (st == RAMBO_OK)
+        st = capture(h, &bg->graph_main, &bg->exec_main, [&](hipStream_t s) {
+            return launch_query_seqs_plain(h, nullptr, nullptr, cap, out, s, default_seg(h->RW), bg->in);
+        });
     if (st != RAMBO_OK) return st;
     res = bg;
     return RAMBO_OK;
@@ -295,7 +328,7 @@ int make_batch_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint
 int launch_batch_graph(rambo_s *h, BatchGraph &bg, hipStream_t s) {
     (void)h;
     HIP_CHECK(hipEventRecord(bg.ev[0], s));
-    HIP_CHECK(hipGraphLaunch(bg.exec_prep, s));
+    if (bg.exec_prep) HIP_CHECK(hipGraphLaunch(bg.exec_prep, s));
     HIP_CHECK(hipEventRecord(bg.ev[1], s));
     HIP_CHECK(hipGraphLaunch(bg.exec_main, s));
     HIP_CHECK(hipEventRecord(bg.ev[2], s));
@@ -319,7 +352,8 @@ static int run_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint
         bg = it->second;
     } else {
         if (h->graphs.size() >= 16) h->graphs.clear();
-        int st = make_batch_graph(h, tu, seqs, offs, n, out, &n, bg);
+        const InputHdr init{n, offs, seqs, 0};
+        int st = make_batch_graph(h, tu, nullptr, &init, n, out, bg);
         if (st != RAMBO_OK) return st;
         h->graphs[key] = bg;
     }

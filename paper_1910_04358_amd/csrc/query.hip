@@ -82,7 +82,13 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
 template <int SEG, int G>
 __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_t *__restrict__ seqs,
                                                           const uint64_t *__restrict__ offs, uint64_t n,
-                                                          uint64_t *__restrict__ out, QueryOpts opt, int use_res) {
+                                                          const InputHdr *hdr, uint64_t *__restrict__ out,
+                                                          QueryOpts opt, int use_res) {
+    if (hdr) {  // batch described in device memory (graph replays)
+        n = hdr->n;
+        offs = hdr->offs;
+        seqs = hdr->seqs;
+    }
     extern __shared__ uint64_t smem64[];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t mwords = (ix.R * ix.RW + 1) & ~1u;
@@ -155,7 +161,8 @@ int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *
 }
 
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                            hipStream_t s, int seg) {
+                            hipStream_t s, int seg, const InputHdr *hdr) {
+    // with hdr, the batch is read on the device and n is only its capacity
     const Index ix = make_index(h);
     const int G = (int)h->RW / seg;
     const int WPB = 4;
@@ -171,7 +178,7 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
-                       n, out, opt, use_res)
+                       n, hdr, out, opt, use_res)
     RAMBO_DISPATCH_SPLIT(seg, G)
 #undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());

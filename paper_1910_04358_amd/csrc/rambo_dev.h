@@ -35,6 +35,16 @@ struct Index {
     uint32_t log2RW, W;      // W = result words per query
 };
 
+// A batch of reads described in device memory, so that one captured graph
+// can serve batches of any size and placement: read i is
+// seqs[offs[i] .. offs[i+1]), i < n. n comes first (scans read it alone).
+struct InputHdr {
+    uint64_t n;
+    const uint64_t *offs;
+    const uint8_t *seqs;
+    uint64_t pad;
+};
+
 // ---------------------------------------------------------------------------
 // Hashing: h_{r,j}(x) = floor(m * hi64((A x + C) mod 2^128) / 2^64)
 // (multiply-add-shift, strongly universal for 62-bit keys; range reduced by

@@ -99,8 +99,10 @@ int launch_dump_bfu(rambo_s *h, uint32_t r, uint32_t b, uint64_t *d_out, hipStre
 
 // query.hip
 int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *out, hipStream_t s);
+// With hdr (device), the batch is read from it on the device and n is only
+// the capacity the grid is sized for.
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
-                            uint64_t *out, hipStream_t s, int seg);
+                            uint64_t *out, hipStream_t s, int seg, const InputHdr *hdr = nullptr);
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off,
                uint64_t ids_cap, hipStream_t s);
 

@@ -37,14 +37,18 @@ struct Request {
     std::shared_ptr<std::vector<uint8_t>> own;  // single submissions own their bytes
 };
 
+// A slot's staging area (pinned on the host, mirrored on the device) holds
+// one batch packed as [InputHdr | offsets (n + 1) | read bytes], so a batch
+// goes to the device in a single copy and the captured graphs find it
+// through the header at the start.
+static constexpr uint64_t kHdrBytes = 256;
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    uint8_t *h_seqs = nullptr, *d_seqs = nullptr;
-    uint64_t *h_offs = nullptr, *d_offs = nullptr;
+    uint8_t *h_stage = nullptr, *d_stage = nullptr;
     uint64_t *h_out = nullptr, *d_out = nullptr;
-    uint64_t *h_n = nullptr;
-    std::shared_ptr<BatchGraph> small, large;  // graphs for small and full batches
+    std::shared_ptr<BatchGraph> small, large;  // plain-kernel graph for small batches, persistent for large
     std::vector<Request> reqs;
     uint64_t budget = 0;
     double t_admit = 0;
@@ -97,17 +101,36 @@ static void server_fail(rambo_server_s *s, int st) {
     s->cv_poll.notify_all();
 }
 
-static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n, uint64_t bytes) {
+// Pack the slot's requests into its staging area; returns the bytes to copy.
+static uint64_t pack_slot(Slot &sl) {
+    const uint64_t n = sl.reqs.size();
+    uint64_t *offs = (uint64_t *)(sl.h_stage + kHdrBytes);
+    uint8_t *bytes = (uint8_t *)(offs + n + 1);
+    uint64_t off = 0;
+    offs[0] = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        memcpy(bytes + off, sl.reqs[i].bytes, sl.reqs[i].len);
+        off += sl.reqs[i].len;
+        offs[i + 1] = off;
+    }
+    InputHdr *hdr = (InputHdr *)sl.h_stage;
+    hdr->n = n;
+    hdr->offs = (const uint64_t *)(sl.d_stage + kHdrBytes);
+    hdr->seqs = sl.d_stage + kHdrBytes + (n + 1) * 8;
+    hdr->pad = 0;
+    return kHdrBytes + (n + 1) * 8 + off;
+}
+
+static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n, uint64_t copy_bytes) {
     rambo_s *h = s->h;
-    HIP_CHECK(hipMemcpyAsync(sl.d_seqs, sl.h_seqs, bytes ? bytes : 1, hipMemcpyHostToDevice, sl.stream));
-    HIP_CHECK(hipMemcpyAsync(sl.d_offs, sl.h_offs, (n + 1) * 8, hipMemcpyHostToDevice, sl.stream));
+    HIP_CHECK(hipMemcpyAsync(sl.d_stage, sl.h_stage, copy_bytes, hipMemcpyHostToDevice, sl.stream));
     int st;
     if (s->cfg.policy == RAMBO_SERVE_SERIAL) {
-        st = launch_query_seqs_plain(h, sl.d_seqs, sl.d_offs, n, sl.d_out, sl.stream, default_seg(h->RW));
+        const uint64_t *offs = (const uint64_t *)(sl.d_stage + kHdrBytes);
+        st = launch_query_seqs_plain(h, sl.d_stage + kHdrBytes + (n + 1) * 8, offs, n, sl.d_out, sl.stream,
+                                     default_seg(h->RW));
     } else {
         BatchGraph &bg = (n <= sl.small->cap) ? *sl.small : *sl.large;
-        *sl.h_n = n;
-        HIP_CHECK(hipMemcpyAsync(bg.d_n, sl.h_n, 8, hipMemcpyHostToDevice, sl.stream));
         st = launch_batch_graph(h, bg, sl.stream);
     }
     if (st != RAMBO_OK) return st;
@@ -158,14 +181,7 @@ static void dispatcher_main(rambo_server_s *s) {
         Slot &sl = s->slots[slot];
         sl.budget = cost;
         sl.t_admit = now_s();
-        uint64_t off = 0;
-        sl.h_offs[0] = 0;
-        for (uint64_t i = 0; i < n; i++) {
-            memcpy(sl.h_seqs + off, sl.reqs[i].bytes, sl.reqs[i].len);
-            off += sl.reqs[i].len;
-            sl.h_offs[i + 1] = off;
-        }
-        int st = launch_slot(s, sl, n, bytes);
+        int st = launch_slot(s, sl, n, pack_slot(sl));
         if (st != RAMBO_OK) {
             server_fail(s, st);
             return;
@@ -280,36 +296,31 @@ static void free_slot(Slot &sl) {
     sl.large.reset();
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    if (sl.h_seqs) (void)hipHostFree(sl.h_seqs);
-    if (sl.h_offs) (void)hipHostFree(sl.h_offs);
+    if (sl.h_stage) (void)hipHostFree(sl.h_stage);
     if (sl.h_out) (void)hipHostFree(sl.h_out);
-    if (sl.h_n) (void)hipHostFree(sl.h_n);
-    if (sl.d_seqs) (void)hipFree(sl.d_seqs);
-    if (sl.d_offs) (void)hipFree(sl.d_offs);
+    if (sl.d_stage) (void)hipFree(sl.d_stage);
     if (sl.d_out) (void)hipFree(sl.d_out);
 }
 
 static int setup_slot(rambo_server_s *s, Slot &sl) {
     rambo_s *h = s->h;
     const uint64_t R = s->cfg.max_batch_reads, BY = s->cfg.max_batch_bytes;
+    const uint64_t stage = kHdrBytes + (R + 1) * 8 + BY;
     HIP_CHECK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
     HIP_CHECK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-    HIP_CHECK(hipHostMalloc((void **)&sl.h_seqs, BY, hipHostMallocDefault));
-    HIP_CHECK(hipHostMalloc((void **)&sl.h_offs, (R + 1) * 8, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void **)&sl.h_stage, stage, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void **)&sl.h_out, R * h->W * 8, hipHostMallocDefault));
-    HIP_CHECK(hipHostMalloc((void **)&sl.h_n, 8, hipHostMallocDefault));
-    HIP_CHECK(hipMalloc(&sl.d_seqs, BY));
-    HIP_CHECK(hipMalloc(&sl.d_offs, (R + 1) * 8));
+    HIP_CHECK(hipMalloc(&sl.d_stage, stage));
     HIP_CHECK(hipMalloc(&sl.d_out, R * h->W * 8));
     if (s->cfg.policy == RAMBO_SERVE_CONTINUOUS) {
+        const InputHdr *in = (const InputHdr *)sl.d_stage;
         Tune large = h->tune;
         if (!h->tuned) large.seg = default_seg(h->RW);
-        // small batches: a grid of about one wave per read
-        Tune small = large;
-        small.waves_per_cu = std::max(small.wpb, 2);
-        const uint64_t small_cap = std::min<uint64_t>(R, (uint64_t)h->n_cu * 2);
-        int st = make_batch_graph(h, small, sl.d_seqs, sl.d_offs, small_cap, sl.d_out, nullptr, sl.small);
-        if (st == RAMBO_OK) st = make_batch_graph(h, large, sl.d_seqs, sl.d_offs, R, sl.d_out, nullptr, sl.large);
+        // small batches: the plain kernel, one wave per read; large ones:
+        // the persistent form with the handle's tuned shape
+        const uint64_t small_cap = std::min<uint64_t>(R, 2048);
+        int st = make_plain_graph(h, in, small_cap, sl.d_out, sl.small);
+        if (st == RAMBO_OK) st = make_batch_graph(h, large, in, nullptr, R, sl.d_out, sl.large);
         if (st != RAMBO_OK) return st;
     }
     return RAMBO_OK;
