@@ -31,7 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
-GRANULE = 64            # bytes one isolated random row read costs at the memory
+# Bytes one isolated random row read moves from HBM: random 16-byte reads over
+# a 40 GiB buffer run 2.4x faster than random 64-byte reads on this GPU (46.6
+# vs 19.2 G reads/s, paper_1910_04358_amd.micro), so the fetch unit of a
+# small random read is a 32-byte sector.
+GRANULE = 32
 
 
 def log(*a):
@@ -76,6 +80,31 @@ def build_index(w, dev, docs_per_chunk=1000):
     del seqs
     torch.cuda.empty_cache()
     return idx, build_ms, kmers
+
+
+def kmer_queries_run(dev, steps, warmup):
+    """Single k-mer queries (plain kernel) on the K = 1,000 workload: 20
+    ancestors x 50 mutants of 200 kbp (1 % substitutions), R=4, B=32,
+    m=2^26, eta=3; 10^7 queries, half windows of documents, half random."""
+    import torch
+    import gen
+
+    w = gen.workload(2)
+    idx, build_ms, build_kmers = build_index(w, dev)
+    q, _ = gen.kmer_queries(w.docs, w.kmer_qseed, w.n_kmer_queries, 0.5)
+    qd = up(q, dev)
+    out = torch.empty((q.size, idx.W), dtype=torch.int64, device=dev)
+    ms = time_steps(lambda: idx.query_kmers(qd, out=out), steps, warmup)
+    probes = q.size * w.R * w.eta
+    rec = {"workload": w.name, "queries": int(q.size), "ms_per_batch": ms, "kmer_per_s": q.size / ms * 1e3,
+           "probes_per_s": probes / ms * 1e3, "out_bytes": int(q.size * idx.W * 8),
+           "build_ms": build_ms, "build_input_GBps_u64_kmers": build_kmers * 8 / build_ms / 1e6}
+    log("k-mer queries (%s): %.3f ms per 10^7, %.3g k-mer/s; build %.0f ms" % (w.name, ms, rec["kmer_per_s"],
+                                                                               build_ms))
+    idx.close()
+    del out, qd
+    torch.cuda.empty_cache()
+    return rec
 
 
 def time_steps(fn, steps, warmup):
@@ -135,6 +164,11 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) runs")
     ap.add_argument("--cpu-reads", type=int, default=6000)
     ap.add_argument("--cpu-docs", type=int, default=1000)
+    ap.add_argument("--tune", default=None,
+                    help="batched launch shape seg,tile,waves_per_cu,wpb,grab (skips the autotuner)")
+    ap.add_argument("--no-kmers", action="store_true", help="skip the single k-mer query workload")
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="also run a 1 GiB device copy (scale for hardware byte counters)")
     ap.add_argument("--only", choices=["plain", "batched"], default=None,
                     help="time only one form (for profiler runs)")
     args = ap.parse_args()
@@ -178,8 +212,11 @@ def main():
         result["plain"] = {"ms_per_step": plain_ms, "kmer_per_s": n_kmers / plain_ms * 1e3,
                            "reads_per_s": reads.n / plain_ms * 1e3, "probes": plain_probes}
     idx.set_mode(MODE_BATCHED)
+    if args.tune:
+        from paper_1910_04358_amd import Tune
+        idx.set_tune(Tune(*[int(v) for v in args.tune.split(",")]))
     t = time.time()
-    step()  # autotunes the launch shape on this batch
+    step()  # autotunes the launch shape on this batch (unless set above)
     torch.cuda.synchronize()
     tune = idx.get_tune()
     log("autotune: %.1fs -> %s" % (time.time() - t, tune))
@@ -211,6 +248,38 @@ def main():
     alg_bytes = issued * max(GRANULE, row_bytes) + io_bytes
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     value = n_kmers / batched_ms * 1e3
+
+    # the empirical ceiling of the probe pattern: uniformly random row reads
+    # over the index's own buffer (random-access microbenchmark)
+    ceiling = None
+    try:
+        from paper_1910_04358_amd import micro
+        import ctypes
+        L = micro.lib()
+        sink = torch.zeros(4096, dtype=torch.int32, device=dev)
+        lay = idx.layout()
+        blocks = torch.cuda.get_device_properties(0).multi_processor_count * 16
+        best = min(L.micro_run(0, ctypes.c_void_p(lay.rows), idx.index_bytes, row_bytes, blocks, 16, 77 + k,
+                               ctypes.c_void_p(sink.data_ptr())) for k in range(3))
+        nload = blocks * 256 * 16 * L.micro_per_lane(0, row_bytes)
+        ceiling = {"probes_per_s": nload / best * 1e3, "GBps": nload / best * 1e3 * max(GRANULE, row_bytes) / 1e9,
+                   "what": "random %d-byte row reads over the %.0f GiB index buffer" % (row_bytes,
+                                                                                      idx.index_bytes / 2**30)}
+        log("random-read ceiling: %.3g probes/s (%.0f GB/s at %d B)" % (ceiling["probes_per_s"], ceiling["GBps"],
+                                                                      max(GRANULE, row_bytes)))
+    except (RuntimeError, OSError) as e:
+        log("random-read ceiling not measured:", e)
+
+    if args.pmc_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    kq = None
+    if not args.no_kmers:
+        kq = kmer_queries_run(dev, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu:
@@ -250,9 +319,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_batch_main", "kernel_ms": kern_ms, "probes_per_launch": issued,
-                     "bytes_per_probe": max(GRANULE, row_bytes), "io_bytes": io_bytes},
+                     "bytes_per_probe": max(GRANULE, row_bytes), "io_bytes": io_bytes,
+                     "random_read_ceiling": ceiling,
+                     "frac_of_ceiling": (issued / (kern_ms * 1e-3) / ceiling["probes_per_s"]) if ceiling else None},
         "cpu_baseline": cpu,
         "served": served,
+        "kmer_queries": kq,
     }
     print(json.dumps(line), flush=True)
     idx.close()

@@ -29,6 +29,7 @@ struct BatchGraph {
     void *mem = nullptr;
     hipGraph_t graph_prep = nullptr, graph_main = nullptr;
     hipGraphExec_t exec_prep = nullptr, exec_main = nullptr;
+    bool timed = false;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // before prep, before main, after main
     ~BatchGraph();
 };
