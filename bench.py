@@ -31,11 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
-# Bytes one isolated random row read moves from HBM: random 16-byte reads over
-# a 40 GiB buffer run 2.4x faster than random 64-byte reads on this GPU (46.6
-# vs 19.2 G reads/s, paper_1910_04358_amd.micro), so the fetch unit of a
-# small random read is a 32-byte sector.
-GRANULE = 32
+# Bytes one isolated random row read moves from HBM on this GPU: the
+# FETCH_SIZE counter reads 64 bytes per random 16-byte load, both for the
+# random-read microbenchmark and for the query kernel.
+GRANULE = 64
 
 
 def log(*a):
@@ -271,11 +270,9 @@ def main():
         log("random-read ceiling not measured:", e)
 
     if args.pmc_copy:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        from paper_1910_04358_amd import micro
+        ms = micro.copy(1 << 30)
+        log("copy kernel: 1 GiB in %.3f ms" % ms)
 
     kq = None
     if not args.no_kmers:

@@ -78,6 +78,27 @@ __global__ __launch_bounds__(256) void k_atomic_or(uint32_t *buf, uint64_t n_wor
     }
 }
 
+// plain streaming copy of n16 16-byte words: the known-size reference for
+// the hardware byte counters (it reads and writes exactly 16 * n16 bytes)
+__global__ __launch_bounds__(256) void k_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, uint64_t n16) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+MICRO_API double micro_copy(void *dst, const void *src, uint64_t bytes, uint32_t blocks) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1;
+    hipEventRecord(a, 0);
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, 0, (uint4 *)dst, (const uint4 *)src, bytes / 16);
+    hipEventRecord(b, 0);
+    if (hipEventSynchronize(b) != hipSuccess) return -3;
+    float ms = 0;
+    hipEventElapsedTime(&ms, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return ms;
+}
+
 // Returns the kernel time in ms (events), or a negative value on error.
 // kind: 0 = gather, 1 = atomic OR. row_bytes: 4, 16, 64 or 128.
 MICRO_API double micro_run(int kind, void *buf, uint64_t bytes, int row_bytes, uint32_t blocks, uint32_t iters,

@@ -67,12 +67,47 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    const bool dense = rmode == RAMBO_RESOLVE_DENSE || res == nullptr || (rmode == RAMBO_RESOLVE_AUTO && ix.W <= 64);
+    if (!dense) {
+        for (int t = 0; t < KPW; t++) {
+            const uint64_t row = base + t;
+            if (row >= n) break;
+            uint64_t *o = out + row * ix.W;
+            if (!((alive >> t) & 1)) write_zeros(o, ix.W, lane);
+            else resolve(ix, M + t * ix.R * ix.RW, res, o, lane, rmode);
+        }
+        return;
+    }
+    // Dense resolve, word by word: the cells phi_r(d) of the word's 64
+    // documents are loaded once and tested against every live term's masks.
+    uint64_t live = alive;
+    if (KPW < 64) live &= (1ULL << KPW) - 1;
+    if (n - base < (uint64_t)KPW) live &= (1ULL << (n - base)) - 1;
     for (int t = 0; t < KPW; t++) {
         const uint64_t row = base + t;
         if (row >= n) break;
-        uint64_t *o = out + row * ix.W;
-        if (!((alive >> t) & 1)) write_zeros(o, ix.W, lane);
-        else resolve(ix, M + t * ix.R * ix.RW, res, o, lane, rmode);
+        if (!((live >> t) & 1)) write_zeros(out + row * ix.W, ix.W, lane);
+    }
+    if (!live) return;
+    for (uint32_t w = 0; w < ix.W; w++) {
+        const uint64_t d = (uint64_t)w * 64 + lane;
+        const bool real = d < ix.K;
+        uint32_t ph[MAXR];
+#pragma unroll
+        for (int r = 0; r < MAXR; r++) ph[r] = (r < (int)ix.R && real) ? ix.phi[(uint64_t)r * ix.K + d] : 0u;
+        uint64_t mine = 0, todo = live;
+        while (todo) {
+            const int t = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t *Mt = M + t * ix.R * ix.RW;
+            uint32_t keep = real ? 1u : 0u;
+#pragma unroll
+            for (int r = 0; r < MAXR; r++)
+                if (r < (int)ix.R) keep &= mask_bit(Mt + r * ix.RW, ph[r]);
+            const uint64_t word = __ballot(keep);
+            if (lane == (uint32_t)t) mine = word;
+        }
+        if ((live >> lane) & 1) out[(base + lane) * ix.W + w] = mine;
     }
 }
 

@@ -26,7 +26,22 @@ def lib():
     L.micro_run.restype = ctypes.c_double
     L.micro_per_lane.argtypes = [ctypes.c_int, ctypes.c_int]
     L.micro_per_lane.restype = ctypes.c_uint32
+    L.micro_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32]
+    L.micro_copy.restype = ctypes.c_double
     return L
+
+
+def copy(nbytes: int = 1 << 30) -> float:
+    """Run the plain copy kernel over nbytes (multiple of 16); returns ms."""
+    import torch
+    L = lib()
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    ms = L.micro_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), nbytes, n_cu * 16)
+    if ms < 0:
+        raise RuntimeError("micro_copy failed")
+    return ms
 
 
 def run(sizes_gib, rows, iters=16, reps=3, atomics=True):
