@@ -31,10 +31,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
-# Bytes one isolated random row read moves from HBM on this GPU: the
-# FETCH_SIZE counter reads 64 bytes per random 16-byte load, both for the
-# random-read microbenchmark and for the query kernel.
-GRANULE = 64
+# Bytes one isolated random row read moves from HBM on this GPU: a read
+# request from L2 to memory carries a 128-byte line (a copy of 1 GiB issues
+# exactly 1 GiB / 128 B read requests; each probe of the query kernel issues
+# one request), see profiles/k_batch_main_K10000_traffic.md.
+GRANULE = 128
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_batch_main_K10000_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the query kernel from the committed counter
+    profile, or None if the kernel's sources changed since it was taken."""
+    import hashlib
+    try:
+        prof = json.load(open(TRAFFIC_PROFILE))
+        h = hashlib.sha256()
+        for s in prof["sources"]:
+            h.update(open(os.path.join(ROOT, s), "rb").read())
+        return prof["traffic_bytes_per_launch"] if h.hexdigest() == prof["sources_sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -314,7 +330,8 @@ def main():
                   "bases_per_s": w.docs.n_docs * w.docs.length / build_ms * 1e3},
         "plain": result.get("plain"),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "useful_bytes_frac": (issued * row_bytes + io_bytes) / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "kernel": "k_batch_main", "kernel_ms": kern_ms, "probes_per_launch": issued,
                      "bytes_per_probe": max(GRANULE, row_bytes), "io_bytes": io_bytes,
                      "random_read_ceiling": ceiling,
