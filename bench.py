@@ -159,6 +159,13 @@ def cpu_baseline(w, sample_reads, sample_docs, nthreads):
     res, tests = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2, early_exit=True, nthreads=nthreads)
     q_s = time.time() - t
     kmers = reads.n_windows()
+    # one thread, the paper's query convention, on the first tenth
+    n1 = max(1, sample_reads // 10)
+    o1 = reads.offsets[: n1 + 1]
+    t = time.time()
+    o.query_seqs(reads.seqs[: int(o1[-1])], o1, oracle.MODE_ALG2, early_exit=True, nthreads=1)
+    one_s = time.time() - t
+    k1 = int(np.maximum(np.diff(o1.astype(np.int64)) - 30, 0).sum())
     del o
     return {"value": kmers / q_s, "unit": "k-mer queries/s", "cores": nthreads, "kind": "oracle",
             "sample": "Algorithm 2 with early exit on %d reads (%d k-mers) drawn from documents 0..%d of the "
@@ -167,7 +174,8 @@ def cpu_baseline(w, sample_reads, sample_docs, nthreads):
                       "query time %.2fs on %d threads (index build %.1fs not counted)"
                       % (sample_reads, kmers, sample_docs - 1, w.R, w.B, int(np.log2(w.m)), w.eta,
                          sample_docs, q_s, nthreads, build_s),
-            "reads_per_s": sample_reads / q_s}
+            "reads_per_s": sample_reads / q_s,
+            "one_thread_kmer_per_s": k1 / one_s}
 
 
 def main():
@@ -177,7 +185,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) runs")
-    ap.add_argument("--cpu-reads", type=int, default=6000)
+    ap.add_argument("--cpu-reads", type=int, default=60000)
+    ap.add_argument("--no-fold", action="store_true", help="skip folding the index at the end")
     ap.add_argument("--cpu-docs", type=int, default=1000)
     ap.add_argument("--tune", default=None,
                     help="batched launch shape seg,tile,waves_per_cu,wpb,grab (skips the autotuner)")
@@ -340,6 +349,22 @@ def main():
         "served": served,
         "kmer_queries": kq,
     }
+    if not args.no_fold and args.only is None:
+        # folding over (B -> B/2, streaming), then the same batch on the folded index
+        idx.set_mode(MODE_PLAIN)
+        before = idx.index_bytes
+        torch.cuda.synchronize()
+        t = time.time()
+        idx.fold()
+        fold_s = time.time() - t
+        moved = before + idx.index_bytes
+        folded_ms = time_steps(step, args.steps, args.warmup)
+        line["fold"] = {"B_after": idx.B, "ms": fold_s * 1e3, "bytes_moved": moved,
+                        "GBps": moved / fold_s / 1e9, "frac_of_hbm_peak": moved / fold_s / 1e9 / HBM_PEAK_GBS,
+                        "plain_ms_per_step_after": folded_ms,
+                        "note": "wall time of the synchronous call (allocation + kernel + table rebuild)"}
+        log("fold: B %d -> %d in %.1f ms (%.0f GB/s incl. allocation); plain step after: %.3f ms"
+            % (w.B, idx.B, fold_s * 1e3, moved / fold_s / 1e9, folded_ms))
     print(json.dumps(line), flush=True)
     idx.close()
 

@@ -168,6 +168,15 @@ int rambo_insert_batch(rambo_t *h, const uint64_t *doc_ids, const uint64_t *kmer
 int rambo_insert_seqs(rambo_t *h, const uint64_t *doc_ids, const uint8_t *seqs,
                       const uint64_t *offsets, uint64_t n_docs, void *stream);
 
+/* Folding over (Section 5.3, Figure 3): OR the BFUs of cells B/2 .. B-1 onto
+ * cells 0 .. B/2-1 in every repetition, leaving an index of B/2 cells with the
+ * same R, m and hash functions (a document's cell becomes phi_r(d) mod B/2),
+ * the same as building with B/2 cells directly. B must be even. Smaller and
+ * faster, with a higher false-positive rate. Allocates the folded rows before
+ * freeing the old ones (needs the folded size free), synchronous; resets the
+ * batched form's launch shape. */
+int rambo_fold(rambo_t *h);
+
 /* ---------------------------------------------------------------------- */
 /* Queries (Algorithm 2, Section 3.3.1)                                    */
 /* ---------------------------------------------------------------------- */

@@ -231,6 +231,49 @@ RAMBO_API int rambo_dump_bfu(rambo_t *h, uint32_t r, uint32_t b, uint64_t *out) 
     return st;
 }
 
+RAMBO_API int rambo_fold(rambo_t *h) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_fold: null handle");
+    if (h->B < 2 || h->B % 2) return fail(RAMBO_EINVAL, "rambo_fold: B=%u is not even", h->B);
+    HIP_CHECK(hipDeviceSynchronize());
+    const uint32_t half = h->B / 2;
+    uint32_t need = (half + 31) / 32, rw = 1, lg = 0;
+    while (rw < need) { rw <<= 1; lg++; }
+    const uint64_t bytes = (uint64_t)h->R * h->m * rw * 4;
+    uint32_t *nrows = nullptr;
+    if (hipMalloc(&nrows, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RAMBO_ENOMEM, "rambo_fold: cannot allocate %llu bytes for the folded index",
+                    (unsigned long long)bytes);
+    }
+    int st = launch_fold(h, h->rows, nrows, h->RW, lg, half, h->aux);
+    if (st == RAMBO_OK && hipStreamSynchronize(h->aux) != hipSuccess) st = fail(RAMBO_EDEVICE, "rambo_fold: kernel failed");
+    if (st != RAMBO_OK) {
+        (void)hipFree(nrows);
+        return st;
+    }
+    (void)hipFree(h->rows);
+    h->rows = nrows;
+    h->RW = rw;
+    h->log2RW = lg;
+    h->rows_bytes = bytes;
+    h->B = half;
+    // the same hash functions with B/2 cells: phi'_r(d) = phi_r(d) mod B/2
+    derive_hashes(h);
+    (void)hipFree(h->d_hp);
+    (void)hipFree(h->d_phi);
+    (void)hipFree(h->d_boff);
+    (void)hipFree(h->d_bdoc);
+    h->d_hp = nullptr;
+    h->d_phi = nullptr;
+    h->d_boff = h->d_bdoc = nullptr;
+    st = upload_tables(h);
+    std::lock_guard<std::mutex> g(h->mu);
+    drop_graphs(h);
+    h->tuned = false;
+    h->tune = Tune();
+    return st;
+}
+
 RAMBO_API int rambo_copy_rows(rambo_t *h, uint64_t offset, uint64_t bytes, void *dst) {
     if (!h || !dst || offset > h->rows_bytes || bytes > h->rows_bytes - offset)
         return fail(RAMBO_EINVAL, "rambo_copy_rows: range outside the index");

@@ -128,3 +128,43 @@ int launch_dump_bfu(rambo_s *h, uint32_t r, uint32_t b, uint64_t *d_out, hipStre
 }
 
 }  // namespace rambo
+
+namespace rambo {
+
+// Folding over (Section 5.3): BFU'(r, b) = BFU(r, b) OR BFU(r, b + B/2) for
+// b < B/2. In the bit-sliced layout this is, per row, the OR of the row's low
+// B/2 bits with its bits [B/2, B) shifted down by B/2. One thread per output
+// word; rows of RWo words (RWo = power of two >= ceil(B/2 / 32)).
+__global__ __launch_bounds__(256) void k_fold(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                              uint64_t rows, uint32_t RWi, uint32_t log2RWo, uint32_t half) {
+    const uint64_t n = rows << log2RWo;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t RWo = 1u << log2RWo;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t row = i >> log2RWo;
+        const uint32_t w = (uint32_t)(i & (RWo - 1));
+        const uint32_t *r = in + row * RWi;
+        const uint32_t b0 = w * 32;  // first output bit of this word
+        uint32_t keep = 0;           // output bits b0 + k with b0 + k < half
+        if (b0 < half) keep = (half - b0 >= 32) ? 0xFFFFFFFFu : ((1u << (half - b0)) - 1u);
+        uint32_t v = 0;
+        if (keep) {
+            const uint32_t lo = (w < RWi) ? r[w] : 0u;
+            const uint32_t hb = half + b0, q = hb >> 5, sh = hb & 31;
+            uint32_t hi = (q < RWi) ? (r[q] >> sh) : 0u;
+            if (sh && q + 1 < RWi) hi |= r[q + 1] << (32 - sh);
+            v = (lo | hi) & keep;
+        }
+        out[i] = v;
+    }
+}
+
+int launch_fold(rambo_s *h, const uint32_t *in, uint32_t *out, uint32_t RWi, uint32_t log2RWo, uint32_t half,
+                hipStream_t s) {
+    const uint64_t rows = (uint64_t)h->R * h->m;
+    hipLaunchKernelGGL(k_fold, dim3((unsigned)h->n_cu * 32), dim3(256), 0, s, in, out, rows, RWi, log2RWo, half);
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+}  // namespace rambo

@@ -50,6 +50,7 @@ SIGNATURES = {
     "rambo_phi_table": ([_vp, _vp], _i32),
     "rambo_dump_bfu": ([_vp, _u32, _u32, _vp], _i32),
     "rambo_copy_rows": ([_vp, _u64, _u64, _vp], _i32),
+    "rambo_fold": ([_vp], _i32),
     "rambo_insert": ([_vp, _u64, _vp, _u64], _i32),
     "rambo_insert_batch": ([_vp, _vp, _vp, _vp, _u64, _vp], _i32),
     "rambo_insert_seqs": ([_vp, _vp, _vp, _vp, _u64, _vp], _i32),
@@ -223,6 +224,12 @@ class Rambo:
                 col = np.concatenate([col, np.zeros((self.R, pad), np.uint8)], axis=1)
             out[:, b, :] = np.packbits(col, axis=1, bitorder="little").view(np.uint64)
         return out
+
+    def fold(self) -> None:
+        """Fold B -> B/2 cells in place (Section 5.3)."""
+        _check(lib().rambo_fold(self._h))
+        lay = self.layout()
+        self.B, self.row_words, self.index_bytes = int(lay.B), int(lay.row_words), int(lay.index_bytes)
 
     # -- construction
     def insert(self, doc_id: int, kmers) -> None:

@@ -215,6 +215,34 @@ def test_build_is_deterministic_and_order_free():
         x.close()
 
 
+@pytest.mark.parametrize("name,folds", [("rw1", 2), ("rw4", 1)])
+def test_fold_matches_oracle(name, folds):
+    """Folding over (Section 5.3) on the GPU equals the oracle's fold: every
+    BFU of the folded index, and every read's answer after folding."""
+    K, B, R, m, eta, dm, rm, nr = CASES[name]
+    idx = rb.Rambo(K, B, R, m, eta, 31337)
+    build_gpu_seqs(idx, dm, 0, K)
+    o = build_oracle((K, B, R, m, eta, 31337), dm)
+    reads = gen.reads(dm, rm, 1500)
+    seqs, offs = reads_to_dev(reads)
+    for _ in range(folds):
+        idx.fold()
+        o = o.fold()
+        assert idx.B == o.B
+        bits = o.bits()
+        for r in range(R):
+            for b in range(idx.B):
+                assert np.array_equal(idx.dump_bfu(r, b), bits[r, b]), (r, b)
+        want, _ = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2)
+        for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+            idx.set_mode(mode)
+            assert np.array_equal(to_host_u64(idx.query_seqs(seqs, offs)), want), (idx.B, mode)
+    with pytest.raises(rb.RamboError):
+        odd = rb.Rambo(10, 5, 2, 1024, 2, 1)
+        odd.fold()
+    idx.close()
+
+
 def test_insert_batch_kmers_equals_sequences():
     K, B, R, m, eta, dm, rm, nr = CASES["rw32"]
     a = rb.Rambo(K, B, R, m, eta, 7)
