@@ -271,6 +271,9 @@ typedef struct {
     uint64_t max_batch_bytes; /* read bytes per batch (slot capacity) */
     uint32_t policy;          /* RAMBO_SERVE_* */
     uint32_t queue_cap;       /* pending reads before submit returns RAMBO_EBUSY */
+    uint32_t direct_below;    /* continuous policy: batches of fewer reads launch
+                                 the plain kernel directly instead of replaying
+                                 the slot's graph (0: always replay) */
 } rambo_server_config_t;
 
 typedef struct {

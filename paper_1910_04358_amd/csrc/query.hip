@@ -78,8 +78,6 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
         }
         return;
     }
-    // Dense resolve, word by word: the cells phi_r(d) of the word's 64
-    // documents are loaded once and tested against every live term's masks.
     uint64_t live = alive;
     if (KPW < 64) live &= (1ULL << KPW) - 1;
     if (n - base < (uint64_t)KPW) live &= (1ULL << (n - base)) - 1;
@@ -89,6 +87,49 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
         if (!((live >> t) & 1)) write_zeros(out + row * ix.W, ix.W, lane);
     }
     if (!live) return;
+    if constexpr (G == 1) {
+        // One lane per term (B <= 128): transposed dense resolve. T[r][c] is
+        // the 64-bit set of the wave's live terms whose repetition-r mask has
+        // cell c; a document's terms are the AND over r of T[r][phi_r(d)],
+        // and a 64 x 64 bit transpose turns the documents' term sets into
+        // the terms' result words.
+        uint64_t *T = reinterpret_cast<uint64_t *>(M);  // R * B words, fits the staging area
+        const bool me_live = (live >> lane) & 1;
+#pragma unroll
+        for (int r = 0; r < MAXR; r++) {
+            if (r < (int)ix.R) {
+                uint64_t t0 = 0, t1 = 0;  // cells lane and 64 + lane
+#pragma unroll
+                for (int wi = 0; wi < SEG; wi++) {
+                    for (uint32_t k = 0; k < 32; k++) {
+                        const uint32_t c = (uint32_t)wi * 32 + k;
+                        if (c >= ix.B) break;
+                        const uint64_t tset = __ballot(me_live && ((acc[r].w[wi] >> k) & 1u));
+                        if ((c & 63) == lane) {
+                            if (c < 64) t0 = tset;
+                            else t1 = tset;
+                        }
+                    }
+                }
+                if (lane < ix.B) T[r * ix.B + lane] = t0;
+                if (64 + lane < ix.B) T[r * ix.B + 64 + lane] = t1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t w = 0; w < ix.W; w++) {
+            const uint64_t d = (uint64_t)w * 64 + lane;
+            uint64_t tm = d < ix.K ? ~0ULL : 0ULL;
+#pragma unroll
+            for (int r = 0; r < MAXR; r++)
+                if (r < (int)ix.R && d < ix.K) tm &= T[r * ix.B + ix.phi[(uint64_t)r * ix.K + d]];
+            const uint64_t col = wave_transpose64(tm, lane);
+            if (me_live) out[(base + lane) * ix.W + w] = col;
+        }
+        return;
+    }
+    // Dense resolve, word by word: the cells phi_r(d) of the word's 64
+    // documents are loaded once and tested against every live term's masks.
     for (uint32_t w = 0; w < ix.W; w++) {
         const uint64_t d = (uint64_t)w * 64 + lane;
         const bool real = d < ix.K;

@@ -185,6 +185,22 @@ __device__ __forceinline__ void set_ones(Seg<SEG> (&acc)[MAXR]) {
         for (int s = 0; s < SEG; s++) acc[r].w[s] = 0xFFFFFFFFu;
 }
 
+// 64 x 64 bit-matrix transpose across a wave: lane i holds row i on entry
+// and column i on exit (bit j of lane i's input = bit i of lane j's output).
+// Six butterfly stages, each swapping the off-diagonal blocks of one size.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, uint32_t lane) {
+    const uint64_t masks[6] = {0x00000000FFFFFFFFULL, 0x0000FFFF0000FFFFULL, 0x00FF00FF00FF00FFULL,
+                               0x0F0F0F0F0F0F0F0FULL, 0x3333333333333333ULL, 0x5555555555555555ULL};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const uint32_t s = 32u >> k;
+        const uint64_t m = masks[k];
+        const uint64_t y = __shfl_xor(x, (int)s);
+        x = (lane & s) ? ((x & ~m) | ((y & ~m) >> s)) : ((x & m) | ((y & m) << s));
+    }
+    return x;
+}
+
 // AND across the k-mer groups of a wave: lanes l and l ^ off (off >= G) hold
 // the same row segment of different terms.
 template <int G>
@@ -292,14 +308,22 @@ __device__ __forceinline__ uint32_t probe_step(const Index &ix, const Window &wv
         *dead = true;
         return 1;
     }
-    Seg<SEG> cm[MAXR];
-#pragma unroll
-    for (int r = 1; r < MAXR; r++)
-        if (r < (int)ix.R) probe_rep_step<SEG, G>(ix, wv, valid, lane, r, cm[r]);
+    // repetitions 1.. in groups of four (one group for R <= 5), all loads of a
+    // group in flight together
+    constexpr int GR = 4;
     bool alive = true;
 #pragma unroll
-    for (int r = 1; r < MAXR; r++)
-        if (r < (int)ix.R) alive &= fold_rep<SEG, G>(cm[r], acc[r]);
+    for (int g0 = 1; g0 < MAXR; g0 += GR) {
+        if (g0 < (int)ix.R && (alive || !early_exit)) {
+            Seg<SEG> cm[GR];
+#pragma unroll
+            for (int k = 0; k < GR; k++)
+                if (g0 + k < MAXR && g0 + k < (int)ix.R) probe_rep_step<SEG, G>(ix, wv, valid, lane, g0 + k, cm[k]);
+#pragma unroll
+            for (int k = 0; k < GR; k++)
+                if (g0 + k < MAXR && g0 + k < (int)ix.R) alive &= fold_rep<SEG, G>(cm[k], acc[g0 + k]);
+        }
+    }
     *dead = early_exit && !alive;
     return ix.R;
 }

@@ -125,7 +125,7 @@ static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n, uint64_t copy_by
     rambo_s *h = s->h;
     HIP_CHECK(hipMemcpyAsync(sl.d_stage, sl.h_stage, copy_bytes, hipMemcpyHostToDevice, sl.stream));
     int st;
-    if (s->cfg.policy == RAMBO_SERVE_SERIAL) {
+    if (s->cfg.policy == RAMBO_SERVE_SERIAL || n < s->cfg.direct_below) {
         const uint64_t *offs = (const uint64_t *)(sl.d_stage + kHdrBytes);
         st = launch_query_seqs_plain(h, sl.d_stage + kHdrBytes + (n + 1) * 8, offs, n, sl.d_out, sl.stream,
                                      default_seg(h->RW));

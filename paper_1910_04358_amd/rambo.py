@@ -79,7 +79,7 @@ SERVE_CONTINUOUS, SERVE_SERIAL = 0, 1
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", _u64), ("slots", _u32), ("max_batch_reads", _u32), ("max_batch_bytes", _u64),
-                ("policy", _u32), ("queue_cap", _u32)]
+                ("policy", _u32), ("queue_cap", _u32), ("direct_below", _u32)]
 
 
 class Completion(ctypes.Structure):
@@ -350,9 +350,9 @@ class Server:
     """Continuous-batching server over a resident index (RAMBO_SERVE_*)."""
 
     def __init__(self, idx: "Rambo", budget_bytes=4 << 30, slots=4, max_batch_reads=8192,
-                 max_batch_bytes=8 << 20, policy=SERVE_CONTINUOUS, queue_cap=1 << 20):
+                 max_batch_bytes=8 << 20, policy=SERVE_CONTINUOUS, queue_cap=1 << 20, direct_below=0):
         self.idx = idx
-        cfg = ServerConfig(budget_bytes, slots, max_batch_reads, max_batch_bytes, policy, queue_cap)
+        cfg = ServerConfig(budget_bytes, slots, max_batch_reads, max_batch_bytes, policy, queue_cap, direct_below)
         self._s = lib().rambo_server_start(idx._h, ctypes.byref(cfg))
         if not self._s:
             raise RamboError(lib().rambo_last_status(), lib().rambo_last_error().decode(errors="replace"))

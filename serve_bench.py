@@ -15,12 +15,13 @@ import numpy as np
 RATES = (1000, 5000, 10000, 25000, 50000)
 
 
-def _serve(idx, reads, arrivals, policy, budget, slots=4, max_batch_reads=8192, max_batch_bytes=8 << 20):
+def _serve(idx, reads, arrivals, policy, budget, slots=4, max_batch_reads=8192, max_batch_bytes=8 << 20,
+           direct_below=0):
     from paper_1910_04358_amd import Server, clock
 
     n = reads.n
     srv = Server(idx, budget_bytes=budget, slots=slots, max_batch_reads=max_batch_reads,
-                 max_batch_bytes=max_batch_bytes, policy=policy)
+                 max_batch_bytes=max_batch_bytes, policy=policy, direct_below=direct_below)
     t0 = clock() + 0.05
     sched = t0 + arrivals
     srv.submit_schedule(reads.seqs, reads.offsets, sched)
@@ -71,13 +72,15 @@ def run(idx, w, dev, log, rates=RATES, seconds=2.0, min_reads=2000, max_reads=10
         offs = torch.from_numpy(reads.offsets.view(np.int64)).to(dev)
         ref = idx.query_seqs(seqs, offs).cpu().numpy().view(np.uint64)
         rec = {"rate": lam, "reads": n}
-        for name, policy in (("served", SERVE_CONTINUOUS), ("serial_plain", SERVE_SERIAL)):
-            m, bits = _serve(idx, reads, arrivals, policy, budget)
+        for name, policy, direct in (("served", SERVE_CONTINUOUS, 0), ("served_direct_small", SERVE_CONTINUOUS, 2049),
+                                     ("serial_plain", SERVE_SERIAL, 0)):
+            m, bits = _serve(idx, reads, arrivals, policy, budget, direct_below=direct)
             if not np.array_equal(bits, ref):
                 raise SystemExit("served results differ from the plain kernel at rate %d (%s)" % (lam, name))
             rec[name] = m
-        log("serve %6d reads/s: served p50 %.3f p99 %.3f ms | serial p50 %.3f p99 %.3f ms"
-            % (lam, rec["served"]["p50_ms"], rec["served"]["p99_ms"], rec["serial_plain"]["p50_ms"],
-               rec["serial_plain"]["p99_ms"]))
+        log("serve %6d reads/s: served p50 %.3f p99 %.3f ms | direct-small p50 %.3f p99 %.3f | serial p50 %.3f "
+            "p99 %.3f ms" % (lam, rec["served"]["p50_ms"], rec["served"]["p99_ms"],
+                             rec["served_direct_small"]["p50_ms"], rec["served_direct_small"]["p99_ms"],
+                             rec["serial_plain"]["p50_ms"], rec["serial_plain"]["p99_ms"]))
         out["rates"].append(rec)
     return out
