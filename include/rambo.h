@@ -228,6 +228,11 @@ typedef struct {
     int waves_per_cu; /* resident waves per compute unit of the persistent grid */
     int wpb;          /* waves per workgroup: 1, 2 or 4 */
     int grab;         /* work items taken per queue access */
+    int sched;        /* probe schedule of a read's windows, same results
+                         under both (Section 3.3.1), also used by the plain
+                         form: 0 = per step of 64 windows, repetition 0 then
+                         the others; 1 = repetition 0 over the whole work
+                         item first, then the others */
     int tuned;        /* output of rambo_get_tune: 1 once chosen or set */
 } rambo_tune_t;
 

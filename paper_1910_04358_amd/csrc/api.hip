@@ -65,7 +65,7 @@ static void derive_hashes(rambo_s *h) {
 static void free_device(rambo_s *h) {
     if (h->rows) (void)hipFree(h->rows);
     if (h->d_hp) (void)hipFree(h->d_hp);
-    if (h->d_phi) (void)hipFree(h->d_phi);
+    if (h->d_cells) (void)hipFree(h->d_cells);
     if (h->d_boff) (void)hipFree(h->d_boff);
     if (h->d_bdoc) (void)hipFree(h->d_bdoc);
     if (h->d_invalid) (void)hipFree(h->d_invalid);
@@ -77,16 +77,18 @@ static int upload_tables(rambo_s *h) {
     HashParams hp;
     memset(&hp, 0, sizeof hp);
     for (uint32_t i = 0; i < h->R * h->eta; i++) {
-        hp.Alo[i] = h->Alo[i]; hp.Ahi[i] = h->Ahi[i];
-        hp.Clo[i] = h->Clo[i]; hp.Chi[i] = h->Chi[i];
+        hp.h[i].alo = h->Alo[i]; hp.h[i].ahi = h->Ahi[i];
+        hp.h[i].clo = h->Clo[i]; hp.h[i].chi = h->Chi[i];
     }
     HIP_CHECK(hipMalloc(&h->d_hp, sizeof hp));
     HIP_CHECK(hipMemcpy(h->d_hp, &hp, sizeof hp, hipMemcpyHostToDevice));
 
-    std::vector<uint16_t> phi16(h->phi.size());
-    for (size_t i = 0; i < phi16.size(); i++) phi16[i] = (uint16_t)h->phi[i];
-    HIP_CHECK(hipMalloc(&h->d_phi, phi16.size() * 2));
-    HIP_CHECK(hipMemcpy(h->d_phi, phi16.data(), phi16.size() * 2, hipMemcpyHostToDevice));
+    // document-major cells: record d holds phi_r(d) at 16-bit slot r (B <= 8192)
+    std::vector<uint16_t> cells((size_t)h->K * 8, 0);
+    for (uint32_t r = 0; r < h->R; r++)
+        for (uint64_t d = 0; d < h->K; d++) cells[d * 8 + r] = (uint16_t)h->phi[(size_t)r * h->K + d];
+    HIP_CHECK(hipMalloc(&h->d_cells, cells.size() * 2));
+    HIP_CHECK(hipMemcpy(h->d_cells, cells.data(), cells.size() * 2, hipMemcpyHostToDevice));
 
     // documents grouped by cell, per repetition (Algorithm 2's DocIDs(M[b, r])),
     // with cell offsets relative to the repetition's slice of bdoc
@@ -131,6 +133,7 @@ RAMBO_API rambo_t *rambo_create(uint64_t K, uint32_t B, uint32_t R, uint64_t m, 
     while (rw < need) { rw <<= 1; lg++; }
     h->RW = rw;
     h->log2RW = lg;
+    h->tune.seg = default_seg(rw);
     h->W = (K + 63) / 64;
     h->rows_bytes = (uint64_t)R * m * rw * 4;
     if (hipGetDevice(&h->device) != hipSuccess ||
@@ -260,17 +263,18 @@ RAMBO_API int rambo_fold(rambo_t *h) {
     // the same hash functions with B/2 cells: phi'_r(d) = phi_r(d) mod B/2
     derive_hashes(h);
     (void)hipFree(h->d_hp);
-    (void)hipFree(h->d_phi);
+    (void)hipFree(h->d_cells);
     (void)hipFree(h->d_boff);
     (void)hipFree(h->d_bdoc);
     h->d_hp = nullptr;
-    h->d_phi = nullptr;
+    h->d_cells = nullptr;
     h->d_boff = h->d_bdoc = nullptr;
     st = upload_tables(h);
     std::lock_guard<std::mutex> g(h->mu);
     drop_graphs(h);
     h->tuned = false;
     h->tune = Tune();
+    h->tune.seg = default_seg(h->RW);
     return st;
 }
 

@@ -58,6 +58,13 @@ __device__ __forceinline__ uint64_t find_read(const uint64_t *off, uint64_t n, u
     return lo;
 }
 
+// a wave-uniform value, kept in scalar registers
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint32_t load_coherent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -71,17 +78,6 @@ __device__ __forceinline__ bool read_dead(const Index &ix, const uint32_t *rm, u
         dead |= __ballot(o != 0) == 0;
     }
     return dead;
-}
-
-// the masks staged in LDS have an empty repetition
-__device__ __forceinline__ bool lds_some_rep_empty(const Index &ix, const uint32_t *M, uint32_t lane) {
-    bool empty = false;
-    for (uint32_t r = 0; r < ix.R; r++) {
-        uint32_t o = 0;
-        for (uint32_t w = lane; w < ix.RW; w += 64) o |= M[r * ix.RW + w];
-        empty |= __ballot(o != 0) == 0;
-    }
-    return empty;
 }
 
 template <int SEG, int G>
@@ -104,7 +100,7 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
     for (;;) {
         uint64_t t0 = 0;
         if (lane == 0) t0 = atomicAdd(bb.head, (unsigned long long)grab);
-        t0 = __shfl(t0, 0);
+        t0 = uniform64(__shfl(t0, 0));
         if (t0 >= total) break;
         const uint64_t t1 = min(total, t0 + grab);
         for (uint64_t t = t0; t < t1; t++) {
@@ -114,11 +110,11 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
                 c = 0;
             } else {
                 const uint64_t u = t - n;
-                i = find_read(bb.extra_off, n, u, lane);
-                c = 1 + (u - bb.extra_off[i]);
+                i = uniform64(find_read(bb.extra_off, n, u, lane));
+                c = uniform64(1 + (u - bb.extra_off[i]));
             }
-            const uint64_t beg = offs[i];
-            uint64_t end = offs[i + 1];
+            const uint64_t beg = uniform64(offs[i]);
+            uint64_t end = uniform64(offs[i + 1]);
             if (end < beg) end = beg;
             const uint64_t nwin = n_windows(beg, end);
             const uint64_t ntiles = nwin ? (nwin + tile - 1) / tile : 1;
@@ -126,38 +122,18 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
             uint64_t *o = out + i * ix.W;
 
             const bool skip = c > 0 && opt.early_exit && read_dead(ix, rm, lane);
-            Seg<SEG> acc[MAXR];
-            set_ones(acc);
+            init_masks(ix, M, lane);
             if (!skip) {
                 const uint64_t w_hi = min(nwin, (c + 1) * (uint64_t)tile);
-                for (uint64_t w = c * (uint64_t)tile; w < w_hi; w += 64) {
-                    const uint64_t p = beg + w + lane;
-                    const uint32_t c0 = p < end ? seqs[p] : 0u;
-                    const uint32_t c1 = (lane < 30 && p + 64 < end) ? seqs[p + 64] : 0u;
-                    const Window wv = extract_windows(c0, c1, lane);
-                    const bool valid = wv.valid && (w + lane < w_hi);
-                    bool dead;
-                    const uint32_t reps = probe_step<SEG, G>(ix, wv, valid, lane, acc, opt.early_exit != 0, &dead);
-                    issued += (uint64_t)__popcll(__ballot(valid)) * reps;
-                    if (dead) break;
-                }
+                issued += probe_windows<SEG, G>(ix, seqs, beg, end, c * (uint64_t)tile, w_hi, lane, M,
+                                                opt.early_exit != 0, opt.sched);
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             if (ntiles == 1) {
-                // the whole read was in this tile: resolve from registers
-                if (some_rep_empty<SEG, G>(acc, ix.R)) {
-                    write_zeros(o, ix.W, lane);
-                } else {
-                    if (lane < (uint32_t)G) {
-#pragma unroll
-                        for (int r = 0; r < MAXR; r++)
-                            if (r < (int)ix.R)
-#pragma unroll
-                                for (int s = 0; s < SEG; s++) M[r * ix.RW + lane * SEG + s] = acc[r].w[s];
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    resolve(ix, M, res, o, lane, opt.rmode);
-                }
+                // the whole read was in this tile: resolve from its masks
+                if (masks_some_rep_empty(ix, M, lane)) write_zeros(o, ix.W, lane);
+                else resolve(ix, M, res, o, lane, opt.rmode);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 continue;
@@ -167,20 +143,17 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
             // of coherence of all XCDs; the workgroup-scope fence between them
             // makes the wave wait for the ANDs to complete before it counts
             // (no L2 write-back is needed: nothing here is a plain store).
-            if (!skip && lane < (uint32_t)G) {
-#pragma unroll
-                for (int r = 0; r < MAXR; r++)
-                    if (r < (int)ix.R)
-#pragma unroll
-                        for (int s = 0; s < SEG; s++)
-                            if (acc[r].w[s] != 0xFFFFFFFFu)
-                                __hip_atomic_fetch_and(rm + r * ix.RW + lane * SEG + s, acc[r].w[s], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (!skip) {
+                for (uint32_t w = lane; w < mw; w += 64) {
+                    const uint32_t v = M[w];
+                    if (v != 0xFFFFFFFFu)
+                        __hip_atomic_fetch_and(rm + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             uint32_t prev = 0;
             if (lane == 0) prev = __hip_atomic_fetch_add(bb.done + i, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            prev = __shfl(prev, 0);
+            prev = __builtin_amdgcn_readfirstlane(__shfl(prev, 0));
             if (prev + 1 == ntiles) {
                 // last tile of read i: every other tile's ANDs were performed
                 // before its count; read the masks with atomic RMWs as well
@@ -189,7 +162,7 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
                     M[w] = __hip_atomic_fetch_or(rm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                if (lds_some_rep_empty(ix, M, lane)) write_zeros(o, ix.W, lane);
+                if (masks_some_rep_empty(ix, M, lane)) write_zeros(o, ix.W, lane);
                 else resolve(ix, M, res, o, lane, opt.rmode);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -221,7 +194,7 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
         use_res = 0;
         lds = (size_t)tu.wpb * mwords * 4;
     }
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched};
     // a persistent grid must be resident: never more workgroups than fit
 #define RAMBO_SPLIT_BODY_                                                                                  \
     {                                                                                                      \
@@ -341,8 +314,8 @@ int launch_batch_graph(rambo_s *h, BatchGraph &bg, hipStream_t s) {
 
 static std::string graph_key(const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out) {
     char buf[256];
-    snprintf(buf, sizeof buf, "%p/%p/%llu/%p/%d.%d.%d.%d.%d", (const void *)seqs, (const void *)offs,
-             (unsigned long long)n, (void *)out, tu.seg, tu.tile, tu.waves_per_cu, tu.wpb, tu.grab);
+    snprintf(buf, sizeof buf, "%p/%p/%llu/%p/%d.%d.%d.%d.%d.%d", (const void *)seqs, (const void *)offs,
+             (unsigned long long)n, (void *)out, tu.seg, tu.tile, tu.waves_per_cu, tu.wpb, tu.grab, tu.sched);
     return buf;
 }
 
@@ -379,7 +352,7 @@ bool tune_valid(const rambo_s *h, const Tune &t) {
     return (t.seg == 1 || t.seg == 2 || t.seg == 4) && (int)h->RW % t.seg == 0 &&
            split_supported(t.seg, (int)h->RW / t.seg) && t.tile >= 64 && t.tile % 64 == 0 && t.tile <= (1 << 20) &&
            t.waves_per_cu >= 1 && t.waves_per_cu <= 64 && (t.wpb == 1 || t.wpb == 2 || t.wpb == 4) && t.grab >= 1 &&
-           t.grab <= 64;
+           t.grab <= 64 && (t.sched == 0 || t.sched == 1);
 }
 
 static std::string tune_key(const rambo_s *h) {
@@ -404,7 +377,8 @@ static bool tune_cache_load(rambo_s *h) {
         const size_t bar = line.find('|');
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         Tune t;
-        if (sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.seg, &t.tile, &t.waves_per_cu, &t.wpb, &t.grab) == 5 &&
+        if (sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d", &t.seg, &t.tile, &t.waves_per_cu, &t.wpb, &t.grab,
+                   &t.sched) == 6 &&
             tune_valid(h, t)) {
             h->tune = t;
             return true;
@@ -418,7 +392,7 @@ static void tune_cache_store(const rambo_s *h) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << tune_key(h) << "|" << h->tune.seg << " " << h->tune.tile << " " << h->tune.waves_per_cu << " "
-      << h->tune.wpb << " " << h->tune.grab << "\n";
+      << h->tune.wpb << " " << h->tune.grab << " " << h->tune.sched << "\n";
 }
 
 static int time_candidate(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
@@ -454,27 +428,28 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
     const char *vb = getenv("RAMBO_TUNE_VERBOSE");
     const bool verbose = vb && vb[0] == '1';
     if (verbose)
-        fprintf(stderr, "rambo autotune: seg=%d tile=%d waves/CU=%d wpb=%d grab=%d -> %.3f ms (start)\n", best.seg,
-                best.tile, best.waves_per_cu, best.wpb, best.grab, best_ms);
+        fprintf(stderr, "rambo autotune: seg=%d tile=%d waves/CU=%d wpb=%d grab=%d sched=%d -> %.3f ms (start)\n",
+                best.seg, best.tile, best.waves_per_cu, best.wpb, best.grab, best.sched, best_ms);
     auto consider = [&](Tune t) -> int {
         if (!tune_valid(h, t)) return RAMBO_OK;
         float ms = 0;
         int st2 = time_candidate(h, t, seqs, offs, n, out, s, ms);
         if (st2 != RAMBO_OK) return st2;
         if (verbose)
-            fprintf(stderr, "rambo autotune: seg=%d tile=%d waves/CU=%d wpb=%d grab=%d -> %.3f ms\n", t.seg, t.tile,
-                    t.waves_per_cu, t.wpb, t.grab, ms);
+            fprintf(stderr, "rambo autotune: seg=%d tile=%d waves/CU=%d wpb=%d grab=%d sched=%d -> %.3f ms\n", t.seg,
+                    t.tile, t.waves_per_cu, t.wpb, t.grab, t.sched, ms);
         if (ms < best_ms * 0.98f) {
             best = t;
             best_ms = ms;
         }
         return RAMBO_OK;
     };
-    for (int tile : {64, 256, 512, 1024}) { Tune t = best; t.tile = tile; if ((st = consider(t))) return st; }
-    for (int wpc : {4, 12, 16, 24, 32}) { Tune t = best; t.waves_per_cu = wpc; if ((st = consider(t))) return st; }
+    for (int tile : {128, 256, 512, 2048}) { Tune t = best; t.tile = tile; if ((st = consider(t))) return st; }
+    for (int wpc : {8, 12, 24, 32}) { Tune t = best; t.waves_per_cu = wpc; if ((st = consider(t))) return st; }
     for (int seg : {1, 2, 4}) { Tune t = best; t.seg = seg; if (t.seg != best.seg && (st = consider(t))) return st; }
     for (int grab : {2, 4, 16}) { Tune t = best; t.grab = grab; if ((st = consider(t))) return st; }
     for (int wpb : {1, 2}) { Tune t = best; t.wpb = wpb; if ((st = consider(t))) return st; }
+    { Tune t = best; t.sched = 1 - best.sched; if ((st = consider(t))) return st; }
     std::lock_guard<std::mutex> g(h->mu);
     h->tune = best;
     drop_graphs(h);  // keep only graphs of the chosen shape
@@ -530,11 +505,12 @@ RAMBO_API int rambo_last_batch_ms(rambo_t *h, float *graph_ms, float *kernel_ms)
 
 RAMBO_API int rambo_get_tune(const rambo_t *h, rambo_tune_t *t) {
     if (!h || !t) return fail(RAMBO_EINVAL, "rambo_get_tune: null argument");
-    t->seg = h->tune.seg ? h->tune.seg : default_seg(h->RW);
+    t->seg = h->tune.seg;
     t->tile = h->tune.tile;
     t->waves_per_cu = h->tune.waves_per_cu;
     t->wpb = h->tune.wpb;
     t->grab = h->tune.grab;
+    t->sched = h->tune.sched;
     t->tuned = h->tuned ? 1 : 0;
     return RAMBO_OK;
 }
@@ -547,6 +523,7 @@ RAMBO_API int rambo_set_tune(rambo_t *h, const rambo_tune_t *t) {
     tu.waves_per_cu = t->waves_per_cu;
     tu.wpb = t->wpb;
     tu.grab = t->grab;
+    tu.sched = t->sched;
     if (!tune_valid(h, tu)) return fail(RAMBO_EINVAL, "rambo_set_tune: launch shape out of range");
     std::lock_guard<std::mutex> g(h->mu);
     h->tune = tu;

@@ -8,10 +8,11 @@
 namespace rambo {
 
 __device__ __forceinline__ void scatter_term(const Index &ix, uint64_t x, uint64_t d) {
+    const uint4 cd = ix.cells[d];
 #pragma unroll
     for (int r = 0; r < MAXR; r++) {
         if (r < (int)ix.R) {
-            const uint32_t b = ix.phi[(uint64_t)r * ix.K + d];
+            const uint32_t b = cell_at(cd, r);
             const uint32_t bit = 1u << (b & 31);
 #pragma unroll
             for (int j = 0; j < MAXETA; j++) {

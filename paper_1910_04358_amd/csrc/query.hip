@@ -119,10 +119,14 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
         __builtin_amdgcn_wave_barrier();
         for (uint32_t w = 0; w < ix.W; w++) {
             const uint64_t d = (uint64_t)w * 64 + lane;
-            uint64_t tm = d < ix.K ? ~0ULL : 0ULL;
+            uint64_t tm = 0;
+            if (d < ix.K) {
+                const uint4 cd = ix.cells[d];
+                tm = ~0ULL;
 #pragma unroll
-            for (int r = 0; r < MAXR; r++)
-                if (r < (int)ix.R && d < ix.K) tm &= T[r * ix.B + ix.phi[(uint64_t)r * ix.K + d]];
+                for (int r = 0; r < MAXR; r++)
+                    if (r < (int)ix.R) tm &= T[r * ix.B + cell_at(cd, r)];
+            }
             const uint64_t col = wave_transpose64(tm, lane);
             if (me_live) out[(base + lane) * ix.W + w] = col;
         }
@@ -133,9 +137,10 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
     for (uint32_t w = 0; w < ix.W; w++) {
         const uint64_t d = (uint64_t)w * 64 + lane;
         const bool real = d < ix.K;
+        const uint4 cd = real ? ix.cells[d] : make_uint4(0u, 0u, 0u, 0u);
         uint32_t ph[MAXR];
 #pragma unroll
-        for (int r = 0; r < MAXR; r++) ph[r] = (r < (int)ix.R && real) ? ix.phi[(uint64_t)r * ix.K + d] : 0u;
+        for (int r = 0; r < MAXR; r++) ph[r] = cell_at(cd, r);
         uint64_t mine = 0, todo = live;
         while (todo) {
             const int t = __builtin_ctzll(todo);
@@ -179,35 +184,17 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
     if (end < beg) end = beg;
     const uint64_t nwin = end - beg >= 31 ? end - beg - 30 : 0;
 
-    Seg<SEG> acc[MAXR];
-    set_ones(acc);
-    uint64_t issued = 0;
-    for (uint64_t c = 0; c < nwin; c += 64) {
-        const uint64_t p = beg + c + lane;
-        const uint32_t c0 = p < end ? seqs[p] : 0u;
-        const uint32_t c1 = (lane < 30 && p + 64 < end) ? seqs[p + 64] : 0u;
-        const Window wv = extract_windows(c0, c1, lane);
-        const bool valid = wv.valid && (c + lane < nwin);
-        bool dead;
-        const uint32_t reps = probe_step<SEG, G>(ix, wv, valid, lane, acc, opt.early_exit != 0, &dead);
-        issued += (uint64_t)__popcll(__ballot(valid)) * reps;
-        if (dead) break;
-    }
+    init_masks(ix, M, lane);
+    const uint64_t issued =
+        probe_windows<SEG, G>(ix, seqs, beg, end, 0, nwin, lane, M, opt.early_exit != 0, opt.sched);
     if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
     uint64_t *o = out + read * ix.W;
-    if (some_rep_empty<SEG, G>(acc, ix.R)) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (masks_some_rep_empty(ix, M, lane)) {
         write_zeros(o, ix.W, lane);
         return;
     }
-    if (lane < (uint32_t)G) {
-#pragma unroll
-        for (int r = 0; r < MAXR; r++)
-            if (r < (int)ix.R)
-#pragma unroll
-                for (int s = 0; s < SEG; s++) M[r * ix.RW + lane * SEG + s] = acc[r].w[s];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
     resolve(ix, M, res, o, lane, opt.rmode);
 }
 
@@ -251,7 +238,7 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     }
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, h->tune.sched};
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
                        n, hdr, out, opt, use_res)

@@ -17,16 +17,20 @@ constexpr int MAXR = 8;
 constexpr int MAXETA = 8;
 constexpr uint64_t MASK62 = (1ULL << 62) - 1;
 
-// Bloom hash parameters h_{r,j}, index r * eta + j.
+// Bloom hash parameters h_{r,j} (A = ahi:alo, C = chi:clo), index
+// r * eta + j; one 32-byte record per hash function (one scalar load).
+struct HashRec {
+    uint64_t alo, ahi, clo, chi;
+};
 struct HashParams {
-    uint64_t Alo[MAXR * MAXETA], Ahi[MAXR * MAXETA], Clo[MAXR * MAXETA], Chi[MAXR * MAXETA];
+    HashRec h[MAXR * MAXETA];
 };
 
 // Everything a kernel needs to address the index (passed by value).
 struct Index {
     uint32_t *rows;          // [R][m][RW]
     const HashParams *hp;    // device
-    const uint16_t *phi;     // [R][K]   phi_r(d)
+    const uint4 *cells;      // [K]      phi_r(d) at 16-bit slot r of record d
     const uint32_t *boff;    // [R][B+1] cell offsets into bdoc
     const uint32_t *bdoc;    // [R][K]   documents grouped by cell, ascending
     uint64_t m;
@@ -34,6 +38,12 @@ struct Index {
     uint32_t B, R, eta, RW;  // RW = 32-bit words per row (power of two)
     uint32_t log2RW, W;      // W = result words per query
 };
+
+// phi_r(d) from document d's cell record
+__device__ __forceinline__ uint32_t cell_at(const uint4 &c, int r) {
+    const uint32_t w = r < 2 ? c.x : r < 4 ? c.y : r < 6 ? c.z : c.w;
+    return (r & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
 
 // A batch of reads described in device memory, so that one captured graph
 // can serve batches of any size and placement: read i is
@@ -50,14 +60,17 @@ struct InputHdr {
 // (multiply-add-shift, strongly universal for 62-bit keys; range reduced by
 // a multiply-high, which is the plain top-bits shift when m = 2^t).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t bloom_pos(const Index &ix, uint32_t i, uint64_t x) {
-    const uint64_t alo = ix.hp->Alo[i], ahi = ix.hp->Ahi[i];
-    const uint64_t clo = ix.hp->Clo[i], chi = ix.hp->Chi[i];
+__device__ __forceinline__ uint64_t bloom_pos(const HashRec &p, uint64_t m, uint64_t x) {
+    const uint64_t alo = p.alo, ahi = p.ahi, clo = p.clo, chi = p.chi;
     const uint64_t lo = alo * x;
     uint64_t hi = __umul64hi(alo, x) + ahi * x;
     const uint64_t lo2 = lo + clo;
     hi += chi + (lo2 < lo ? 1 : 0);
-    return __umul64hi(hi, ix.m);
+    return __umul64hi(hi, m);
+}
+
+__device__ __forceinline__ uint64_t bloom_pos(const Index &ix, uint32_t i, uint64_t x) {
+    return bloom_pos(ix.hp->h[i], ix.m, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -155,28 +168,6 @@ __device__ __forceinline__ const uint32_t *row_ptr(const Index &ix, uint32_t r, 
     return ix.rows + (((uint64_t)r * ix.m + pos) << ix.log2RW);
 }
 
-// Probe term x in every BFU of every repetition: per repetition r, the AND
-// over j of rows (r, h_{r,j}(x)) -- the Bloom test of all B BFUs at once
-// (Section 2.1, Section 3.3). This lane's segment `seg` of each masked row
-// is ANDed into acc[r].
-template <int SEG>
-__device__ __forceinline__ void probe_and(const Index &ix, uint64_t x, uint32_t seg, Seg<SEG> (&acc)[MAXR]) {
-#pragma unroll
-    for (int r = 0; r < MAXR; r++) {
-        if (r < (int)ix.R) {
-#pragma unroll
-            for (int j = 0; j < MAXETA; j++) {
-                if (j < (int)ix.eta) {
-                    const uint64_t pos = bloom_pos(ix, (uint32_t)r * ix.eta + j, x);
-                    const Seg<SEG> v = load_seg<SEG>(row_ptr(ix, r, pos) + seg * SEG);
-#pragma unroll
-                    for (int s = 0; s < SEG; s++) acc[r].w[s] &= v.w[s];
-                }
-            }
-        }
-    }
-}
-
 template <int SEG>
 __device__ __forceinline__ void set_ones(Seg<SEG> (&acc)[MAXR]) {
 #pragma unroll
@@ -239,93 +230,242 @@ __device__ __forceinline__ bool some_rep_empty(const Seg<SEG> (&acc)[MAXR], uint
     return empty;
 }
 
-// Probe term x in repetition r only: AND over j of rows (r, h_{r,j}(x)),
-// this lane's segment.
-template <int SEG>
-__device__ __forceinline__ void probe_rep(const Index &ix, uint64_t x, uint32_t seg, int r, Seg<SEG> &acc) {
+// Rows of term x in repetitions FIRST .. FIRST+COUNT-1 (those below R), with
+// ETA hash functions each: all loads issued before any is used (so a wave
+// keeps COUNT * ETA row reads in flight), then ANDed into cm -- per
+// repetition the Bloom test of all B BFUs at once (Section 2.1, Section 3.3).
+// This lane's segment seg of each row.
+// cm[OFF + k] receives repetition FIRST + k.
+template <int SEG, int FIRST, int COUNT, int ETA, int OFF, int N>
+__device__ __forceinline__ void probe_reps_eta(const Index &ix, const HashRec *hp, uint64_t x, uint32_t seg,
+                                               Seg<SEG> (&cm)[N]) {
+    static_assert(OFF + COUNT <= N, "repetition group past the masks");
+    Seg<SEG> v[COUNT][ETA];
 #pragma unroll
-    for (int j = 0; j < MAXETA; j++) {
-        if (j < (int)ix.eta) {
-            const uint64_t pos = bloom_pos(ix, (uint32_t)r * ix.eta + j, x);
-            const Seg<SEG> v = load_seg<SEG>(row_ptr(ix, r, pos) + seg * SEG);
+    for (int k = 0; k < COUNT; k++) {
+        if (FIRST + k < (int)ix.R) {
 #pragma unroll
-            for (int s = 0; s < SEG; s++) acc.w[s] &= v.w[s];
+            for (int j = 0; j < ETA; j++) {
+                const uint64_t pos = bloom_pos(hp[(FIRST + k) * ETA + j], ix.m, x);
+                v[k][j] = load_seg<SEG>(row_ptr(ix, FIRST + k, pos) + seg * SEG);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < COUNT; k++)
+        if (FIRST + k < (int)ix.R)
+#pragma unroll
+            for (int j = 0; j < ETA; j++)
+#pragma unroll
+                for (int s = 0; s < SEG; s++) cm[OFF + k].w[s] &= v[k][j].w[s];
+}
+
+// As probe_reps_eta for any eta (up to MAXETA): one row at a time.
+template <int SEG, int FIRST, int COUNT, int OFF, int N>
+__device__ __forceinline__ void probe_reps_any(const Index &ix, const HashRec *hp, uint64_t x, uint32_t seg,
+                                               Seg<SEG> (&cm)[N]) {
+#pragma unroll
+    for (int k = 0; k < COUNT; k++) {
+        if (FIRST + k < (int)ix.R) {
+#pragma unroll 1
+            for (int j = 0; j < (int)ix.eta; j++) {
+                const uint64_t pos = bloom_pos(hp[(FIRST + k) * ix.eta + j], ix.m, x);
+                const Seg<SEG> v = load_seg<SEG>(row_ptr(ix, FIRST + k, pos) + seg * SEG);
+#pragma unroll
+                for (int s = 0; s < SEG; s++) cm[OFF + k].w[s] &= v.w[s];
+            }
         }
     }
 }
 
-// Probe one term in repetition r into cm (the lanes of a term group split the
-// row); for G > 1 the group's term is fetched from the lane that extracted it.
+template <int SEG, int FIRST, int COUNT, int OFF = 0, int N>
+__device__ __forceinline__ void probe_reps(const Index &ix, const HashRec *hp, uint64_t x, uint32_t seg,
+                                           Seg<SEG> (&cm)[N]) {
+    switch (ix.eta) {
+    case 1: probe_reps_eta<SEG, FIRST, COUNT, 1, OFF, N>(ix, hp, x, seg, cm); break;
+    case 2: probe_reps_eta<SEG, FIRST, COUNT, 2, OFF, N>(ix, hp, x, seg, cm); break;
+    case 3: probe_reps_eta<SEG, FIRST, COUNT, 3, OFF, N>(ix, hp, x, seg, cm); break;
+    default: probe_reps_any<SEG, FIRST, COUNT, OFF, N>(ix, hp, x, seg, cm); break;
+    }
+}
+
+// The hash parameter table, re-derived at every step of a probe loop: the
+// compiler then reloads a group's parameters (one scalar load per hash) at
+// each step instead of hoisting every repetition's parameters out of the
+// loop, which would hold them all in scalar registers at once and spill.
+__device__ __forceinline__ const HashRec *step_params(const Index &ix) {
+    uint32_t z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return ix.hp->h + z;
+}
+
+// Probe term x in every BFU of every repetition: per repetition r, the AND
+// over j of rows (r, h_{r,j}(x)) -- the Bloom test of all B BFUs at once
+// (Section 2.1, Section 3.3). This lane's segment `seg` of each masked row
+// is ANDed into acc[r]; the rows of four repetitions are read together.
+template <int SEG>
+__device__ __forceinline__ void probe_and(const Index &ix, uint64_t x, uint32_t seg, Seg<SEG> (&acc)[MAXR]) {
+    probe_reps<SEG, 0, 4, 0>(ix, ix.hp->h, x, seg, acc);
+    if (ix.R > 4) probe_reps<SEG, 4, MAXR - 4, 4>(ix, ix.hp->h, x, seg, acc);
+}
+
+// AND a repetition's step mask across the wave into its running mask Mr
+// (RW words in the wave's LDS area; lane l of a term group owns words
+// (l mod G) * SEG ..); returns whether the running mask is still non-empty
+// (wave-uniform).
 template <int SEG, int G>
-__device__ __forceinline__ void probe_rep_step(const Index &ix, const Window &wv, bool valid, uint32_t lane, int r,
-                                               Seg<SEG> &cm) {
+__device__ __forceinline__ bool fold_rep(const Seg<SEG> &cm, uint32_t *Mr, uint32_t lane) {
+    const uint64_t group0 = (G >= 64) ? ~0ULL : ((1ULL << G) - 1);
+    const uint32_t base = (lane % G) * SEG;
+    uint32_t o = 0;
 #pragma unroll
-    for (int s = 0; s < SEG; s++) cm.w[s] = 0xFFFFFFFFu;
+    for (int s = 0; s < SEG; s++) {
+        uint32_t prev = Mr[base + s];
+        if constexpr (G == 1) prev = __builtin_amdgcn_readfirstlane(prev);
+        const uint32_t v = and_across_groups<G>(cm.w[s]) & prev;
+        if (lane < (uint32_t)G) Mr[base + s] = v;
+        o |= v;
+    }
+    if constexpr (G == 1) return o != 0;  // uniform already
+    else return (__ballot(o != 0) & group0) != 0;
+}
+
+// Running masks of all repetitions (the wave's LDS area M, R * RW words) to
+// all ones: nothing excluded yet.
+__device__ __forceinline__ void init_masks(const Index &ix, uint32_t *M, uint32_t lane) {
+    for (uint32_t w = lane; w < ix.R * ix.RW; w += 64) M[w] = 0xFFFFFFFFu;
+}
+
+// Some repetition's running mask in M is empty (wave-uniform): the read's
+// answer is empty.
+__device__ __forceinline__ bool masks_some_rep_empty(const Index &ix, const uint32_t *M, uint32_t lane) {
+    bool empty = false;
+    for (uint32_t r = 0; r < ix.R; r++) {
+        uint32_t o = 0;
+        for (uint32_t w = lane; w < ix.RW; w += 64) o |= M[r * ix.RW + w];
+        empty |= __ballot(o != 0) == 0;
+    }
+    return empty;
+}
+
+// Probe repetitions FIRST .. FIRST+COUNT-1 (those below R) with all their
+// loads in flight together and AND them into the running masks; returns
+// whether every one of those running masks is still non-empty.
+template <int SEG, int G, int FIRST, int COUNT>
+__device__ __forceinline__ bool probe_group(const Index &ix, const HashRec *hp, const Window &wv, bool valid,
+                                            uint32_t lane, uint32_t *M) {
+    static_assert(FIRST + COUNT <= MAXR, "repetition group past MAXR");
+    Seg<SEG> cm[COUNT];
+#pragma unroll
+    for (int k = 0; k < COUNT; k++)
+#pragma unroll
+        for (int s = 0; s < SEG; s++) cm[k].w[s] = 0xFFFFFFFFu;
     if constexpr (G == 1) {
-        if (valid) probe_rep<SEG>(ix, wv.canon, 0, r, cm);
+        if (valid) probe_reps<SEG, FIRST, COUNT>(ix, hp, wv.canon, 0, cm);
     } else {
+        // the lanes of a term group split the row: the group's term comes
+        // from the lane that extracted it
         constexpr int KPW = 64 / G;
 #pragma unroll 1
         for (int sub = 0; sub < G; sub++) {
             const int src = sub * KPW + (int)(lane / G);
             const uint64_t x = __shfl(wv.canon, src);
             const int v = __shfl((int)valid, src);
-            if (v) probe_rep<SEG>(ix, x, lane % G, r, cm);
+            if (v) probe_reps<SEG, FIRST, COUNT>(ix, hp, x, lane % G, cm);
         }
     }
-}
-
-// AND a repetition's step mask across the wave into the running mask;
-// returns whether the running mask is still non-empty.
-template <int SEG, int G>
-__device__ __forceinline__ bool fold_rep(const Seg<SEG> &cm, Seg<SEG> &acc) {
-    const uint64_t group0 = (G >= 64) ? ~0ULL : ((1ULL << G) - 1);
-    uint32_t o = 0;
-#pragma unroll
-    for (int s = 0; s < SEG; s++) {
-        acc.w[s] &= and_across_groups<G>(cm.w[s]);
-        o |= acc.w[s];
-    }
-    if constexpr (G == 1) return o != 0;  // uniform already
-    else return (__ballot(o != 0) & group0) != 0;
-}
-
-// One step of 64 windows: repetition 0 first, then the other repetitions
-// together (their loads all in flight at once). The step's masks are ANDed
-// across the wave (G lanes share a term) into the read's running masks acc.
-// With early exit the step stops once a running mask is empty -- the read's
-// answer is then empty whatever the other repetitions hold (Section 3.3.1);
-// random and erroneous reads mostly end at repetition 0 of their first
-// step. Returns the number of repetitions probed; *dead tells whether the
-// read ended.
-template <int SEG, int G>
-__device__ __forceinline__ uint32_t probe_step(const Index &ix, const Window &wv, bool valid, uint32_t lane,
-                                               Seg<SEG> (&acc)[MAXR], bool early_exit, bool *dead) {
-    *dead = false;
-    Seg<SEG> cm0;
-    probe_rep_step<SEG, G>(ix, wv, valid, lane, 0, cm0);
-    if (!fold_rep<SEG, G>(cm0, acc[0]) && early_exit) {
-        *dead = true;
-        return 1;
-    }
-    // repetitions 1.. in groups of four (one group for R <= 5), all loads of a
-    // group in flight together
-    constexpr int GR = 4;
     bool alive = true;
 #pragma unroll
-    for (int g0 = 1; g0 < MAXR; g0 += GR) {
-        if (g0 < (int)ix.R && (alive || !early_exit)) {
-            Seg<SEG> cm[GR];
-#pragma unroll
-            for (int k = 0; k < GR; k++)
-                if (g0 + k < MAXR && g0 + k < (int)ix.R) probe_rep_step<SEG, G>(ix, wv, valid, lane, g0 + k, cm[k]);
-#pragma unroll
-            for (int k = 0; k < GR; k++)
-                if (g0 + k < MAXR && g0 + k < (int)ix.R) alive &= fold_rep<SEG, G>(cm[k], acc[g0 + k]);
+    for (int k = 0; k < COUNT; k++)
+        if (FIRST + k < (int)ix.R) alive &= fold_rep<SEG, G>(cm[k], M + (FIRST + k) * ix.RW, lane);
+    return alive;
+}
+
+// Probe schedules of a read's windows (both give the same running masks)
+enum : int {
+    SCHED_STEP = 0,   // per step of 64 windows: repetition 0, then the others
+    SCHED_SWEEP = 1,  // repetition 0 over every step of the span, then the others
+};
+
+// The bytes lane needs for the 64 windows of step w (window indices relative
+// to the read start beg): base beg+w+lane, and base beg+w+64+lane for the
+// lanes whose windows run past the step.
+struct StepBytes {
+    uint32_t c0, c1;
+};
+__device__ __forceinline__ StepBytes load_bytes(const uint8_t *__restrict__ seqs, uint64_t beg, uint64_t end,
+                                                uint64_t w, uint32_t lane) {
+    const uint64_t p = beg + w + lane;
+    return {p < end ? (uint32_t)seqs[p] : 0u, (lane < 30 && p + 64 < end) ? (uint32_t)seqs[p + 64] : 0u};
+}
+
+// Probe windows [w_lo, w_hi) of the read held in seqs[beg, end) into the
+// running masks in M, 64 windows per step; the step's masks are ANDed across
+// the wave (G lanes share a term). With early exit the probing stops once a
+// running mask is empty: the read's answer is then empty whatever the other
+// rows hold (Section 3.3.1). Under SCHED_STEP each step probes repetition 0
+// and then, if the read is still alive, the others. SCHED_SWEEP follows the
+// repetition-major order of that section over the whole span: repetition 0
+// over every step first, then the others over every step; a read whose answer
+// is empty (a random read, a read with a sequencing error) mostly ends within
+// repetition 0, without the other repetitions' rows for the windows before
+// its first mismatch. The next step's bytes are loaded while the current step
+// probes. Returns the number of (window, repetition) probes the wave issued.
+template <int SEG, int G>
+__device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t *__restrict__ seqs, uint64_t beg,
+                                                  uint64_t end, uint64_t w_lo, uint64_t w_hi, uint32_t lane,
+                                                  uint32_t *M, bool early_exit, int sched) {
+    uint64_t issued = 0;
+    if (sched == SCHED_SWEEP && ix.R > 1) {
+        {
+            StepBytes next = load_bytes(seqs, beg, end, w_lo, lane);
+            for (uint64_t w = w_lo; w < w_hi; w += 64) {
+                const StepBytes cur = next;
+                if (w + 64 < w_hi) next = load_bytes(seqs, beg, end, w + 64, lane);
+                const Window wv = extract_windows(cur.c0, cur.c1, lane);
+                const bool valid = wv.valid && (w + lane < w_hi);
+                const bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid, lane, M);
+                issued += (uint64_t)__popcll(__ballot(valid));
+                if (early_exit && !alive) return issued;
+            }
         }
+        StepBytes next = load_bytes(seqs, beg, end, w_lo, lane);
+        for (uint64_t w = w_lo; w < w_hi; w += 64) {
+            const StepBytes cur = next;
+            if (w + 64 < w_hi) next = load_bytes(seqs, beg, end, w + 64, lane);
+            const Window wv = extract_windows(cur.c0, cur.c1, lane);
+            const bool valid = wv.valid && (w + lane < w_hi);
+            const uint64_t nv = (uint64_t)__popcll(__ballot(valid));
+            bool alive = probe_group<SEG, G, 1, 4>(ix, step_params(ix), wv, valid, lane, M);
+            issued += nv * (min(ix.R, 5u) - 1);
+            if ((int)ix.R > 5 && (alive || !early_exit)) {
+                alive &= probe_group<SEG, G, 5, MAXR - 5>(ix, step_params(ix), wv, valid, lane, M);
+                issued += nv * (ix.R - 5);
+            }
+            if (early_exit && !alive) return issued;
+        }
+        return issued;
     }
-    *dead = early_exit && !alive;
-    return ix.R;
+    StepBytes next = load_bytes(seqs, beg, end, w_lo, lane);
+    for (uint64_t w = w_lo; w < w_hi; w += 64) {
+        const StepBytes cur = next;
+        if (w + 64 < w_hi) next = load_bytes(seqs, beg, end, w + 64, lane);
+        const Window wv = extract_windows(cur.c0, cur.c1, lane);
+        const bool valid = wv.valid && (w + lane < w_hi);
+        const uint64_t nv = (uint64_t)__popcll(__ballot(valid));
+        bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid, lane, M);
+        issued += nv;
+        if (alive || !early_exit) {
+            alive &= probe_group<SEG, G, 1, 4>(ix, step_params(ix), wv, valid, lane, M);
+            issued += nv * (min(ix.R, 5u) - 1);
+            if ((int)ix.R > 5 && (alive || !early_exit)) {
+                alive &= probe_group<SEG, G, 5, MAXR - 5>(ix, step_params(ix), wv, valid, lane, M);
+                issued += nv * (ix.R - 5);
+            }
+        }
+        if (early_exit && !alive) return issued;
+    }
+    return issued;
 }
 
 // ---------------------------------------------------------------------------
@@ -346,19 +486,38 @@ __device__ __forceinline__ uint32_t mask_bit(const uint32_t *M, uint32_t b) {
     return (M[b >> 5] >> (b & 31)) & 1u;
 }
 
+// Document d's cells are all set in the masks M (repetitions FIRST..R-1).
+template <int FIRST>
+__device__ __forceinline__ bool doc_kept(const Index &ix, const uint32_t *M, const uint4 &cd) {
+    bool keep = true;
+#pragma unroll
+    for (int r = FIRST; r < MAXR; r++)
+        if (r < (int)ix.R) keep = keep && mask_bit(M + r * ix.RW, cell_at(cd, r));
+    return keep;
+}
+
 // Dense: every document tests its R cells; lane l handles document 64 w + l
-// and a ballot forms result word w.
+// and a ballot forms result word w. Four words' cell records are loaded
+// together.
 __device__ __forceinline__ void resolve_dense(const Index &ix, const uint32_t *M, uint64_t *out, uint32_t lane) {
+    constexpr uint32_t U = 4;
     for (uint32_t w0 = 0; w0 < ix.W; w0 += 64) {
         uint64_t mine = 0;
         const uint32_t nw = min(64u, ix.W - w0);
-        for (uint32_t t = 0; t < nw; t++) {
-            const uint64_t d = (uint64_t)(w0 + t) * 64 + lane;
-            bool keep = d < ix.K;
-            for (uint32_t r = 0; r < ix.R && keep; r++)
-                keep = mask_bit(M + r * ix.RW, ix.phi[(uint64_t)r * ix.K + d]);
-            const uint64_t word = __ballot(keep);
-            if (lane == t) mine = word;
+        for (uint32_t t = 0; t < nw; t += U) {
+            uint4 cd[U];
+            bool real[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++) {
+                const uint64_t d = (uint64_t)(w0 + t + u) * 64 + lane;
+                real[u] = t + u < nw && d < ix.K;
+                cd[u] = real[u] ? ix.cells[d] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++) {
+                const uint64_t word = __ballot(real[u] && doc_kept<0>(ix, M, cd[u]));
+                if (lane == t + u) mine = word;
+            }
         }
         if (lane < nw) out[w0 + lane] = mine;
     }
@@ -366,25 +525,60 @@ __device__ __forceinline__ void resolve_dense(const Index &ix, const uint32_t *M
 
 // Candidate: only documents of positive repetition-0 cells can survive the
 // intersection (Algorithm 2); each is tested in repetitions 1..R-1 and set in
-// an LDS bitset `res` (W words), which is then written out.
+// an LDS bitset `res` (W words), which is then written out. The candidates
+// are spread over the lanes: per 64 cells, lane l takes cell c0 + l (its
+// range of bdoc), a prefix sum over the lanes numbers the candidates, and
+// each lane then tests candidates k = lane, lane + 64, ... -- the cell range
+// loads, the document ids and their cell records each take one round trip
+// for up to 128 candidates.
 __device__ __forceinline__ void resolve_candidates(const Index &ix, const uint32_t *M, uint64_t *res,
                                                    uint64_t *out, uint32_t lane) {
     for (uint32_t w = lane; w < ix.W; w += 64) res[w] = 0;
-    __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    for (uint32_t wi = 0; wi < ix.RW; wi++) {
-        uint32_t bits = M[wi] & cell_mask(ix, wi);
-        while (bits) {
-            const uint32_t b = wi * 32 + (uint32_t)__builtin_ctz(bits);
-            bits &= bits - 1;
-            const uint32_t beg = ix.boff[b], end = ix.boff[b + 1];
-            for (uint32_t i = beg + lane; i < end; i += 64) {
-                const uint32_t d = ix.bdoc[i];
-                bool keep = true;
-                for (uint32_t r = 1; r < ix.R && keep; r++)
-                    keep = mask_bit(M + r * ix.RW, ix.phi[(uint64_t)r * ix.K + d]);
-                if (keep) atomicOr((unsigned long long *)&res[d >> 6], 1ULL << (d & 63));
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t c0 = 0; c0 < ix.B; c0 += 64) {
+        const uint32_t b = c0 + lane;
+        const bool set = b < ix.B && mask_bit(M, b);
+        if (__ballot(set) == 0) continue;
+        uint32_t beg = 0, len = 0;
+        if (set) {
+            beg = ix.boff[b];
+            len = ix.boff[b + 1] - beg;
+        }
+        uint32_t incl = len;  // inclusive prefix sum of len over the lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(incl, off);
+            if ((int)lane >= off) incl += t;
+        }
+        const uint32_t total = __shfl(incl, 63);
+        const uint32_t excl = incl - len;
+        for (uint32_t k0 = 0; k0 < total; k0 += 128) {
+            uint32_t pos[2];
+            bool has[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const uint32_t k = k0 + (uint32_t)u * 64 + lane;
+                has[u] = k < total;
+                // owner: the number of lanes whose inclusive sum is <= k (its
+                // range holds candidate k; all lanes take part in the search)
+                uint32_t lo = 0;
+#pragma unroll
+                for (uint32_t st = 32; st; st >>= 1)
+                    if (__shfl(incl, (int)(lo + st - 1)) <= k) lo += st;
+                const uint32_t ob = __shfl(beg, (int)lo), oe = __shfl(excl, (int)lo);
+                pos[u] = has[u] ? ob + (k - oe) : 0u;
             }
+            uint32_t d[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) d[u] = has[u] ? ix.bdoc[pos[u]] : 0u;
+            uint4 cd[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) cd[u] = has[u] ? ix.cells[d[u]] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int u = 0; u < 2; u++)
+                if (has[u] && doc_kept<1>(ix, M, cd[u]))
+                    atomicOr((unsigned long long *)&res[d[u] >> 6], 1ULL << (d[u] & 63));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -392,17 +586,12 @@ __device__ __forceinline__ void resolve_candidates(const Index &ix, const uint32
     for (uint32_t w = lane; w < ix.W; w += 64) out[w] = res[w];
 }
 
-__device__ __forceinline__ uint64_t popcount_cells(const Index &ix, const uint32_t *M0) {
-    uint64_t n = 0;
-    for (uint32_t wi = 0; wi < ix.RW; wi++) {
-        uint32_t bits = M0[wi] & cell_mask(ix, wi);
-        while (bits) {
-            const uint32_t b = wi * 32 + (uint32_t)__builtin_ctz(bits);
-            bits &= bits - 1;
-            n += ix.boff[b + 1] - ix.boff[b];
-        }
-    }
-    return n;
+// Number of candidates of the repetition-0 cells set in M, estimated from the
+// number of cells (documents spread evenly over the B cells).
+__device__ __forceinline__ uint64_t estimate_candidates(const Index &ix, const uint32_t *M0) {
+    uint64_t cells = 0;
+    for (uint32_t wi = 0; wi < ix.RW; wi++) cells += __popc(M0[wi] & cell_mask(ix, wi));
+    return cells * ((ix.K + ix.B - 1) / ix.B);
 }
 
 // resolve: 0 auto, 1 dense, 2 candidate (res == nullptr forces dense)
@@ -411,7 +600,7 @@ __device__ __forceinline__ void resolve(const Index &ix, const uint32_t *M, uint
     bool cand = false;
     if (res != nullptr) {
         if (mode == 2) cand = true;
-        else if (mode == 0) cand = popcount_cells(ix, M) * (ix.R - 1) * 2 < ix.K * ix.R;
+        else if (mode == 0) cand = estimate_candidates(ix, M) * (ix.R - 1) * 2 < ix.K * ix.R;
     }
     if (cand) resolve_candidates(ix, M, res, out, lane);
     else resolve_dense(ix, M, out, lane);

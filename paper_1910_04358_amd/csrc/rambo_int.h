@@ -32,10 +32,11 @@ int ok();                                     // clears nothing, returns RAMBO_O
 // Launch shape of the sequence-query kernels; what the autotuner searches.
 struct Tune {
     int seg = 4;          // 32-bit words of a row one lane reads (1, 2 or 4)
-    int tile = 128;       // windows per work item (multiple of 64), batched form
-    int waves_per_cu = 8; // resident waves per CU of the persistent grid
+    int tile = 1024;      // windows per work item (multiple of 64), batched form
+    int waves_per_cu = 16; // resident waves per CU of the persistent grid
     int wpb = 4;          // waves per workgroup
     int grab = 1;         // work items taken per queue access
+    int sched = 1;        // probe schedule of a read's windows (SCHED_*; 1 = sweep)
 };
 
 struct BatchGraph;  // batched-form state for one set of buffers (batch.hip)
@@ -49,7 +50,7 @@ struct rambo_s {
     uint64_t rows_bytes = 0;
     uint32_t *rows = nullptr;
     rambo::HashParams *d_hp = nullptr;
-    uint16_t *d_phi = nullptr;
+    uint4 *d_cells = nullptr;  // [K] phi_r(d) of every repetition, 16 bits each
     uint32_t *d_boff = nullptr, *d_bdoc = nullptr;
     unsigned long long *d_invalid = nullptr;
     std::vector<uint64_t> pa, pb, Alo, Ahi, Clo, Chi;
@@ -70,7 +71,7 @@ inline Index make_index(const rambo_s *h) {
     Index ix;
     ix.rows = h->rows;
     ix.hp = h->d_hp;
-    ix.phi = h->d_phi;
+    ix.cells = h->d_cells;
     ix.boff = h->d_boff;
     ix.bdoc = h->d_bdoc;
     ix.m = h->m;
@@ -88,6 +89,7 @@ struct QueryOpts {
     int rmode;                    // RAMBO_RESOLVE_*
     int early_exit;
     unsigned long long *probes;   // may be null
+    int sched;                    // probe schedule (SCHED_*)
 };
 
 // build.hip

@@ -34,7 +34,7 @@ class Layout(ctypes.Structure):
 
 class TuneC(ctypes.Structure):
     _fields_ = [("seg", _i32), ("tile", _i32), ("waves_per_cu", _i32), ("wpb", _i32), ("grab", _i32),
-                ("tuned", _i32)]
+                ("sched", _i32), ("tuned", _i32)]
 
 
 SIGNATURES = {
@@ -153,6 +153,7 @@ class Tune:
     waves_per_cu: int
     wpb: int
     grab: int
+    sched: int = 0
     tuned: bool = False
 
 
@@ -335,10 +336,10 @@ class Rambo:
     def get_tune(self) -> Tune:
         t = TuneC()
         _check(lib().rambo_get_tune(self._h, ctypes.byref(t)))
-        return Tune(t.seg, t.tile, t.waves_per_cu, t.wpb, t.grab, bool(t.tuned))
+        return Tune(t.seg, t.tile, t.waves_per_cu, t.wpb, t.grab, t.sched, bool(t.tuned))
 
     def set_tune(self, tune: Tune) -> None:
-        t = TuneC(tune.seg, tune.tile, tune.waves_per_cu, tune.wpb, tune.grab, 1)
+        t = TuneC(tune.seg, tune.tile, tune.waves_per_cu, tune.wpb, tune.grab, tune.sched, 1)
         _check(lib().rambo_set_tune(self._h, ctypes.byref(t)))
 
 

@@ -110,9 +110,13 @@ def test_read_queries_every_form_bit_exact(name):
             idx.set_resolve(resolve)
             for ee in (True, False):
                 idx.set_early_exit(ee)
-                got = to_host_u64(idx.query_seqs(seqs, offs))
-                bad = np.nonzero((got != want).any(axis=1))[0]
-                assert bad.size == 0, (name, mode, resolve, ee, bad[:5])
+                for sched in (0, 1):
+                    t = idx.get_tune()
+                    t.sched = sched
+                    idx.set_tune(t)
+                    got = to_host_u64(idx.query_seqs(seqs, offs))
+                    bad = np.nonzero((got != want).any(axis=1))[0]
+                    assert bad.size == 0, (name, mode, resolve, ee, sched, bad[:5])
     idx.set_early_exit(True)
     idx.set_resolve(rb.RESOLVE_AUTO)
     idx.set_mode(rb.MODE_PLAIN)
@@ -126,10 +130,11 @@ def test_batched_launch_shapes_agree(name):
     idx.set_mode(rb.MODE_BATCHED)
     segs = [s for s in (1, 2, 4) if idx.row_words % s == 0 and idx.row_words // s <= 64]
     for seg in segs:
-        for tile, wpc, wpb, grab in ((64, 4, 1, 1), (128, 8, 4, 2), (512, 32, 2, 4)):
-            idx.set_tune(rb.Tune(seg, tile, wpc, wpb, grab))
+        for tile, wpc, wpb, grab, sched in ((64, 4, 1, 1, 0), (128, 8, 4, 2, 1), (512, 32, 2, 4, 1),
+                                            (256, 16, 2, 1, 0), (1024, 16, 4, 1, 1)):
+            idx.set_tune(rb.Tune(seg, tile, wpc, wpb, grab, sched))
             got = to_host_u64(idx.query_seqs(seqs, offs))
-            assert np.array_equal(got, want), (seg, tile, wpc, wpb, grab)
+            assert np.array_equal(got, want), (seg, tile, wpc, wpb, grab, sched)
     idx.set_mode(rb.MODE_PLAIN)
 
 
@@ -256,3 +261,36 @@ def test_insert_batch_kmers_equals_sequences():
     assert np.array_equal(a.copy_rows(), b.copy_rows())
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("name", ["rw4", "rw32"])
+def test_probe_counter_closed_form_without_early_exit(name):
+    """Without early exit every schedule probes each valid window in every
+    repetition with every hash: the counter reads sum(valid windows) * R * eta
+    exactly, in both forms; with early exit it reads no more than that."""
+    import torch
+    idx, o, dm, reads, want = setup_case(name)
+    seqs, offs = reads_to_dev(reads)
+    n_valid = sum(_ref.seq_terms(reads.read(i)).size for i in range(reads.n))
+    full = n_valid * idx.R * idx.eta
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    idx.set_probe_counter(counter)
+    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+        idx.set_mode(mode)
+        for ee in (False, True):
+            idx.set_early_exit(ee)
+            for sched in (0, 1):
+                t = idx.get_tune()
+                t.sched = sched
+                idx.set_tune(t)
+                counter.zero_()
+                got = to_host_u64(idx.query_seqs(seqs, offs))
+                assert np.array_equal(got, want), (mode, ee, sched)
+                c = int(counter.item())
+                if ee:
+                    assert 0 < c <= full, (mode, sched, c, full)
+                else:
+                    assert c == full, (mode, sched, c, full)
+    idx.set_probe_counter(None)
+    idx.set_early_exit(True)
+    idx.set_mode(rb.MODE_PLAIN)
