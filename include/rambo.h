@@ -232,7 +232,8 @@ typedef struct {
                          under both (Section 3.3.1), also used by the plain
                          form: 0 = per step of 64 windows, repetition 0 then
                          the others; 1 = repetition 0 over the whole work
-                         item first, then the others */
+                         item first, then the others; 2 = as 1, after
+                         repetition 0 on every 31st window of the item */
     int tuned;        /* output of rambo_get_tune: 1 once chosen or set */
 } rambo_tune_t;
 

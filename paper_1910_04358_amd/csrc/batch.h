@@ -12,7 +12,10 @@ struct BatchBufs {
     uint32_t *done;            // [cap] finished tiles per multi-tile read
     uint64_t *extra;           // [cap] tiles beyond the first, per read
     uint64_t *extra_off;       // [cap + 1] exclusive scan of extra
+    uint32_t *order;           // [4][cap] reads by size class of their first tile
+    unsigned long long *cls;   // [4] reads per size class
     unsigned long long *head;  // queue position
+    uint64_t cap;
 };
 
 // Captured graphs for one batch description: prep (per-read tile counts and

@@ -28,19 +28,45 @@ __device__ __forceinline__ uint64_t n_windows(uint64_t beg, uint64_t end) {
     return end >= beg + 31 ? end - beg - 30 : 0;
 }
 
+// Queue order of the persistent kernel, longest work first so that the last
+// items to start are short. Class c holds the reads whose first tile has
+// [c, c+1) quarters of a tile of windows (class 3 up to a full tile, which
+// includes every multi-tile read). Order: class 3 first tiles, then every
+// extra tile (tiles 1.. of multi-tile reads; after their read's first tile,
+// which may empty the read's masks and let them skip), then classes 2, 1, 0.
+__global__ void k_batch_reset(BatchBufs bb) {
+    if (threadIdx.x == 0) *bb.head = 0;
+    if (threadIdx.x < 4) bb.cls[threadIdx.x] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t mw, uint32_t tile, BatchBufs bb) {
     const uint64_t n = in->n;
     const uint64_t *__restrict__ offs = in->offs;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *bb.head = 0;
-    if (i >= n) return;
-    const uint64_t beg = offs[i], end = offs[i + 1];
-    const uint64_t nw = n_windows(beg, end > beg ? end : beg);
-    const uint64_t tiles = nw ? (nw + tile - 1) / tile : 1;
-    bb.extra[i] = tiles - 1;
-    if (tiles > 1) {
-        bb.done[i] = 0;
-        for (uint32_t w = 0; w < mw; w++) bb.rmask[i * mw + w] = 0xFFFFFFFFu;
+    const uint32_t lane = threadIdx.x & 63;
+    const bool real = i < n;
+    uint32_t cls = 0;
+    if (real) {
+        const uint64_t beg = offs[i], end = offs[i + 1];
+        const uint64_t nw = n_windows(beg, end > beg ? end : beg);
+        const uint64_t tiles = nw ? (nw + tile - 1) / tile : 1;
+        bb.extra[i] = tiles - 1;
+        if (tiles > 1) {
+            bb.done[i] = 0;
+            for (uint32_t w = 0; w < mw; w++) bb.rmask[i * mw + w] = 0xFFFFFFFFu;
+        }
+        cls = (uint32_t)min<uint64_t>(3, min<uint64_t>(nw, tile) * 4 / tile);
+    }
+    // one atomic per class and wave for the slots of the wave's reads
+    for (uint32_t v = 0; v < 4; v++) {
+        const uint64_t mask = __ballot(real && cls == v);
+        if (!mask) continue;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        unsigned long long base = 0;
+        if ((int)lane == leader) base = atomicAdd(bb.cls + v, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader);
+        if (real && cls == v)
+            bb.order[(uint64_t)v * bb.cap + base + __popcll(mask & ((1ULL << lane) - 1))] = (uint32_t)i;
     }
 }
 
@@ -86,16 +112,18 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
                                                     uint32_t grab) {
     const uint8_t *__restrict__ seqs = in->seqs;
     const uint64_t *__restrict__ offs = in->offs;
-    extern __shared__ uint64_t smem64[];
+    extern __shared__ __align__(16) uint64_t smem64[];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t mw = ix.R * ix.RW;
-    const uint32_t mwords = (mw + 1) & ~1u;
-    const uint32_t per_wave = mwords + (use_res ? 2 * ix.W : 0);
-    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * per_wave;
-    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + mwords) : nullptr;
+    const WaveLds L = wave_lds(mw, ix.W, use_res != 0, opt.sched == SCHED_SCOUT);
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * L.total;
+    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + L.res) : nullptr;
+    uint8_t *stage = opt.sched == SCHED_SCOUT ? reinterpret_cast<uint8_t *>(M + L.stage) : nullptr;
 
     const uint64_t n = in->n;
-    const uint64_t total = n + bb.extra_off[n];
+    const uint64_t n_extra = bb.extra_off[n];
+    const uint64_t total = n + n_extra;
+    const uint64_t c3 = uniform64(bb.cls[3]), c2 = uniform64(bb.cls[2]), c1 = uniform64(bb.cls[1]);
     uint64_t issued = 0;
     for (;;) {
         uint64_t t0 = 0;
@@ -104,14 +132,20 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
         if (t0 >= total) break;
         const uint64_t t1 = min(total, t0 + grab);
         for (uint64_t t = t0; t < t1; t++) {
-            uint64_t i, c;
-            if (t < n) {
-                i = t;
-                c = 0;
-            } else {
-                const uint64_t u = t - n;
+            uint64_t i, c = 0;
+            if (t >= c3 && t < c3 + n_extra) {
+                const uint64_t u = t - c3;
                 i = uniform64(find_read(bb.extra_off, n, u, lane));
                 c = uniform64(1 + (u - bb.extra_off[i]));
+            } else {
+                uint64_t u = t, v = 3;
+                if (u >= c3) {
+                    u -= c3 + n_extra;
+                    v = 2;
+                    if (u >= c2) { u -= c2; v = 1; }
+                    if (v == 1 && u >= c1) { u -= c1; v = 0; }
+                }
+                i = uniform64(bb.order[v * bb.cap + u]);
             }
             const uint64_t beg = uniform64(offs[i]);
             uint64_t end = uniform64(offs[i + 1]);
@@ -121,12 +155,13 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
             uint32_t *rm = bb.rmask + i * mw;
             uint64_t *o = out + i * ix.W;
 
-            const bool skip = c > 0 && opt.early_exit && read_dead(ix, rm, lane);
+            // another tile of the read may have emptied its masks already
+            const bool skip = ntiles > 1 && opt.early_exit && read_dead(ix, rm, lane);
             init_masks(ix, M, lane);
             if (!skip) {
                 const uint64_t w_hi = min(nwin, (c + 1) * (uint64_t)tile);
                 issued += probe_windows<SEG, G>(ix, seqs, beg, end, c * (uint64_t)tile, w_hi, lane, M,
-                                                opt.early_exit != 0, opt.sched);
+                                                opt.early_exit != 0, opt.sched, stage);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -176,6 +211,8 @@ static constexpr uint32_t kMaxLds = 64 * 1024;
 
 static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, hipStream_t s) {
     const uint32_t mw = h->R * h->RW;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bg.bb);
+    HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, bg.in, mw,
                        (uint32_t)tu.tile, bg.bb);
     HIP_CHECK(hipGetLastError());
@@ -187,12 +224,12 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
     const int G = (int)h->RW / tu.seg;
-    const uint32_t mwords = (mw + 1) & ~1u;
+    const bool stage = tu.sched == SCHED_SCOUT;
     int use_res = 1;
-    size_t lds = (size_t)tu.wpb * (mwords + 2 * h->W) * 4;
+    size_t lds = (size_t)tu.wpb * wave_lds(mw, h->W, true, stage).total * 4;
     if (lds > kMaxLds) {
         use_res = 0;
-        lds = (size_t)tu.wpb * mwords * 4;
+        lds = (size_t)tu.wpb * wave_lds(mw, h->W, false, stage).total * 4;
     }
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched};
     // a persistent grid must be resident: never more workgroups than fit
@@ -241,22 +278,27 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
                              const InputHdr *init) {
     const size_t mw = (size_t)h->R * h->RW;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t b_mask = 0, b_done = 0, b_extra = 0, b_off = 0, b_parts = 0;
+    size_t b_mask = 0, b_done = 0, b_extra = 0, b_off = 0, b_parts = 0, b_order = 0;
     if (batch_bufs) {
         b_mask = al(cap * mw * 4);
         b_done = al(cap * 4);
         b_extra = al(cap * 8);
         b_off = al((cap + 1) * 8);
         b_parts = al(scan_parts_needed(cap) * 8);
+        b_order = al(4 * cap * 4);
     }
-    HIP_CHECK(hipMalloc(&bg.mem, b_mask + b_done + b_extra + b_off + b_parts + 512));
+    HIP_CHECK(hipMalloc(&bg.mem, b_mask + b_done + b_extra + b_off + b_parts + b_order + 512));
     char *p = (char *)bg.mem;
     bg.parts = (uint64_t *)p; p += b_parts;
     bg.bb.rmask = (uint32_t *)p; p += b_mask;
     bg.bb.done = (uint32_t *)p; p += b_done;
     bg.bb.extra = (uint64_t *)p; p += b_extra;
     bg.bb.extra_off = (uint64_t *)p; p += b_off;
-    bg.bb.head = (unsigned long long *)p; p += 256;
+    bg.bb.order = (uint32_t *)p; p += b_order;
+    bg.bb.head = (unsigned long long *)p;  // its own 128-byte line (every wave's queue atomic)
+    bg.bb.cls = bg.bb.head + 16;           // [4], the next line
+    p += 256;
+    bg.bb.cap = cap;
     if (in_dev) {
         bg.in = in_dev;
     } else {
@@ -352,7 +394,7 @@ bool tune_valid(const rambo_s *h, const Tune &t) {
     return (t.seg == 1 || t.seg == 2 || t.seg == 4) && (int)h->RW % t.seg == 0 &&
            split_supported(t.seg, (int)h->RW / t.seg) && t.tile >= 64 && t.tile % 64 == 0 && t.tile <= (1 << 20) &&
            t.waves_per_cu >= 1 && t.waves_per_cu <= 64 && (t.wpb == 1 || t.wpb == 2 || t.wpb == 4) && t.grab >= 1 &&
-           t.grab <= 64 && (t.sched == 0 || t.sched == 1);
+           t.grab <= 64 && t.sched >= 0 && t.sched <= 2;
 }
 
 static std::string tune_key(const rambo_s *h) {
@@ -449,7 +491,7 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
     for (int seg : {1, 2, 4}) { Tune t = best; t.seg = seg; if (t.seg != best.seg && (st = consider(t))) return st; }
     for (int grab : {2, 4, 16}) { Tune t = best; t.grab = grab; if ((st = consider(t))) return st; }
     for (int wpb : {1, 2}) { Tune t = best; t.wpb = wpb; if ((st = consider(t))) return st; }
-    { Tune t = best; t.sched = 1 - best.sched; if ((st = consider(t))) return st; }
+    for (int sched : {0, 1, 2}) { Tune t = best; t.sched = sched; if (sched != best.sched && (st = consider(t))) return st; }
     std::lock_guard<std::mutex> g(h->mu);
     h->tune = best;
     drop_graphs(h);  // keep only graphs of the chosen shape

@@ -170,12 +170,12 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
         offs = hdr->offs;
         seqs = hdr->seqs;
     }
-    extern __shared__ uint64_t smem64[];
+    extern __shared__ __align__(16) uint64_t smem64[];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t mwords = (ix.R * ix.RW + 1) & ~1u;
-    const uint32_t per_wave = mwords + (use_res ? 2 * ix.W : 0);
-    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * per_wave;
-    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + mwords) : nullptr;
+    const WaveLds L = wave_lds(ix.R * ix.RW, ix.W, use_res != 0, opt.sched == SCHED_SCOUT);
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * L.total;
+    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + L.res) : nullptr;
+    uint8_t *stage = opt.sched == SCHED_SCOUT ? reinterpret_cast<uint8_t *>(M + L.stage) : nullptr;
 
     const uint64_t read = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (read >= n) return;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
 
     init_masks(ix, M, lane);
     const uint64_t issued =
-        probe_windows<SEG, G>(ix, seqs, beg, end, 0, nwin, lane, M, opt.early_exit != 0, opt.sched);
+        probe_windows<SEG, G>(ix, seqs, beg, end, 0, nwin, lane, M, opt.early_exit != 0, opt.sched, stage);
     if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
     uint64_t *o = out + read * ix.W;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -229,12 +229,12 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     const Index ix = make_index(h);
     const int G = (int)h->RW / seg;
     const int WPB = 4;
-    const uint32_t mwords = (h->R * h->RW + 1) & ~1u;
+    const bool stage = h->tune.sched == SCHED_SCOUT;
     int use_res = 1;
-    size_t lds = (size_t)WPB * (mwords + 2 * h->W) * 4;
+    size_t lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, true, stage).total * 4;
     if (lds > kMaxLds) {
         use_res = 0;
-        lds = (size_t)WPB * mwords * 4;
+        lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, false, stage).total * 4;
     }
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");

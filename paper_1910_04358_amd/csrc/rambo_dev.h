@@ -55,6 +55,24 @@ struct InputHdr {
     uint64_t pad;
 };
 
+// Per-wave LDS area of the sequence query kernels, in 32-bit words: the
+// running masks (R * RW words, rounded to 16 bytes), the candidate bitset
+// (W 64-bit words, rounded to 16 bytes) when use_res, and the byte staging
+// area of the scout schedule when stage. Host and device use this one layout.
+constexpr uint32_t kStageWords = 528;  // 2112 bytes: 64 windows 31 apart, +30, +alignment
+struct WaveLds {
+    uint32_t masks, res, stage, total;  // word offsets and size
+};
+__host__ __device__ inline WaveLds wave_lds(uint32_t mask_words, uint64_t W, bool use_res, bool stage) {
+    WaveLds l;
+    l.masks = 0;
+    l.res = (mask_words + 3u) & ~3u;
+    const uint32_t resw = use_res ? (uint32_t)((2 * W + 3) & ~3ull) : 0u;
+    l.stage = l.res + resw;
+    l.total = l.stage + (stage ? kStageWords : 0u);
+    return l;
+}
+
 // ---------------------------------------------------------------------------
 // Hashing: h_{r,j}(x) = floor(m * hi64((A x + C) mod 2^128) / 2^64)
 // (multiply-add-shift, strongly universal for 62-bit keys; range reduced by
@@ -381,11 +399,64 @@ __device__ __forceinline__ bool probe_group(const Index &ix, const HashRec *hp, 
     return alive;
 }
 
-// Probe schedules of a read's windows (both give the same running masks)
+// Probe schedules of a read's windows (all give the same running masks)
 enum : int {
     SCHED_STEP = 0,   // per step of 64 windows: repetition 0, then the others
     SCHED_SWEEP = 1,  // repetition 0 over every step of the span, then the others
+    SCHED_SCOUT = 2,  // as SWEEP, after repetition 0 on every 31st window
 };
+
+// Scout windows of a span [w_lo, w_hi): w_lo, w_lo + 31, ... and the last
+// window. Windows 31 apart cover every base of the span, so a read holding
+// a base no indexed document has there (a sequencing error, a random read)
+// mostly ends on them.
+__device__ __forceinline__ uint64_t scout_count(uint64_t w_lo, uint64_t w_hi) {
+    const uint64_t span = w_hi - w_lo;  // > 0
+    return (span + 30) / 31 + ((span - 1) % 31 != 0 ? 1 : 0);
+}
+__device__ __forceinline__ uint64_t scout_pos(uint64_t w_lo, uint64_t w_hi, uint64_t i) {
+    return min(w_lo + 31 * i, w_hi - 1);
+}
+__device__ __forceinline__ bool is_scout(uint64_t w_lo, uint64_t w_hi, uint64_t w) {
+    return (w - w_lo) % 31 == 0 || w == w_hi - 1;
+}
+
+// Bytes [lo, hi) of seqs (inside one read) to the wave's LDS staging area,
+// keeping the global 16-byte alignment: byte lo lands at buf[addr(lo) & 15].
+// Whole 16-byte blocks inside [lo, hi) are copied with one load each, the
+// blocks at the two ends byte by byte (nothing outside the read is read).
+__device__ __forceinline__ void stage_bytes(const uint8_t *__restrict__ seqs, uint64_t lo, uint64_t hi, uint8_t *buf,
+                                            uint32_t lane) {
+    const uint8_t *first = seqs + lo, *last = seqs + hi;
+    const uint8_t *base = reinterpret_cast<const uint8_t *>(reinterpret_cast<uintptr_t>(first) & ~(uintptr_t)15);
+    const uint64_t nb = (uint64_t)(last - base + 15) / 16;
+    for (uint64_t k = lane; k < nb; k += 64) {
+        const uint8_t *a = base + 16 * k;
+        uint8_t *dst = buf + 16 * k;
+        if (a >= first && a + 16 <= last) {
+            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(a);
+        } else {
+            for (int i = 0; i < 16; i++)
+                if (a + i >= first && a + i < last) dst[i] = a[i];
+        }
+    }
+}
+
+// The window of 31 bytes at p (LDS), encoded and made canonical.
+__device__ __forceinline__ Window window_at(const uint8_t *p) {
+    uint64_t x = 0;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 31; i++) {
+        const uint32_t c = p[i];
+        ok = ok && base_ok(c);
+        x = (x << 2) | base_code(c);
+    }
+    Window w;
+    w.valid = ok;
+    w.canon = canonical(x & MASK62);
+    return w;
+}
 
 // The bytes lane needs for the 64 windows of step w (window indices relative
 // to the read start beg): base beg+w+lane, and base beg+w+64+lane for the
@@ -414,16 +485,41 @@ __device__ __forceinline__ StepBytes load_bytes(const uint8_t *__restrict__ seqs
 template <int SEG, int G>
 __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t *__restrict__ seqs, uint64_t beg,
                                                   uint64_t end, uint64_t w_lo, uint64_t w_hi, uint32_t lane,
-                                                  uint32_t *M, bool early_exit, int sched) {
+                                                  uint32_t *M, bool early_exit, int sched, uint8_t *stage) {
     uint64_t issued = 0;
-    if (sched == SCHED_SWEEP && ix.R > 1) {
+    const bool scout = sched == SCHED_SCOUT && stage != nullptr && w_lo < w_hi;
+    if (scout) {
+        const uint64_t ns = scout_count(w_lo, w_hi);
+        for (uint64_t i0 = 0; i0 < ns; i0 += 64) {
+            const uint64_t i1 = min(ns, i0 + 64);
+            const uint64_t p0 = scout_pos(w_lo, w_hi, i0);
+            const uint64_t b_lo = beg + p0, b_hi = beg + scout_pos(w_lo, w_hi, i1 - 1) + 31;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // earlier reads of the area are done
+            __builtin_amdgcn_wave_barrier();
+            stage_bytes(seqs, b_lo, b_hi, stage, lane);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            Window wv;
+            wv.canon = 0;
+            wv.valid = false;
+            if (i0 + lane < i1) {
+                const uint32_t q = (uint32_t)(reinterpret_cast<uintptr_t>(seqs + b_lo) & 15) +
+                                   (uint32_t)(scout_pos(w_lo, w_hi, i0 + lane) - p0);
+                wv = window_at(stage + q);
+            }
+            const bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, wv.valid, lane, M);
+            issued += (uint64_t)__popcll(__ballot(wv.valid));
+            if (early_exit && !alive) return issued;
+        }
+    }
+    if ((sched == SCHED_SWEEP || scout) && ix.R > 1) {
         {
             StepBytes next = load_bytes(seqs, beg, end, w_lo, lane);
             for (uint64_t w = w_lo; w < w_hi; w += 64) {
                 const StepBytes cur = next;
                 if (w + 64 < w_hi) next = load_bytes(seqs, beg, end, w + 64, lane);
                 const Window wv = extract_windows(cur.c0, cur.c1, lane);
-                const bool valid = wv.valid && (w + lane < w_hi);
+                const bool valid = wv.valid && (w + lane < w_hi) && !(scout && is_scout(w_lo, w_hi, w + lane));
                 const bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid, lane, M);
                 issued += (uint64_t)__popcll(__ballot(valid));
                 if (early_exit && !alive) return issued;
@@ -452,9 +548,11 @@ __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t
         if (w + 64 < w_hi) next = load_bytes(seqs, beg, end, w + 64, lane);
         const Window wv = extract_windows(cur.c0, cur.c1, lane);
         const bool valid = wv.valid && (w + lane < w_hi);
+        // (with one repetition a scout pass has probed its windows already)
+        const bool valid0 = valid && !(scout && is_scout(w_lo, w_hi, w + lane));
+        bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid0, lane, M);
+        issued += (uint64_t)__popcll(__ballot(valid0));
         const uint64_t nv = (uint64_t)__popcll(__ballot(valid));
-        bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid, lane, M);
-        issued += nv;
         if (alive || !early_exit) {
             alive &= probe_group<SEG, G, 1, 4>(ix, step_params(ix), wv, valid, lane, M);
             issued += nv * (min(ix.R, 5u) - 1);

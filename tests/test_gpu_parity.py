@@ -110,7 +110,7 @@ def test_read_queries_every_form_bit_exact(name):
             idx.set_resolve(resolve)
             for ee in (True, False):
                 idx.set_early_exit(ee)
-                for sched in (0, 1):
+                for sched in (0, 1, 2):
                     t = idx.get_tune()
                     t.sched = sched
                     idx.set_tune(t)
@@ -131,7 +131,8 @@ def test_batched_launch_shapes_agree(name):
     segs = [s for s in (1, 2, 4) if idx.row_words % s == 0 and idx.row_words // s <= 64]
     for seg in segs:
         for tile, wpc, wpb, grab, sched in ((64, 4, 1, 1, 0), (128, 8, 4, 2, 1), (512, 32, 2, 4, 1),
-                                            (256, 16, 2, 1, 0), (1024, 16, 4, 1, 1)):
+                                            (256, 16, 2, 1, 0), (1024, 16, 4, 1, 1), (64, 8, 4, 1, 2),
+                                            (1024, 16, 2, 2, 2)):
             idx.set_tune(rb.Tune(seg, tile, wpc, wpb, grab, sched))
             got = to_host_u64(idx.query_seqs(seqs, offs))
             assert np.array_equal(got, want), (seg, tile, wpc, wpb, grab, sched)
@@ -279,7 +280,7 @@ def test_probe_counter_closed_form_without_early_exit(name):
         idx.set_mode(mode)
         for ee in (False, True):
             idx.set_early_exit(ee)
-            for sched in (0, 1):
+            for sched in (0, 1, 2):
                 t = idx.get_tune()
                 t.sched = sched
                 idx.set_tune(t)
