@@ -279,7 +279,9 @@ typedef struct {
     uint32_t queue_cap;       /* pending reads before submit returns RAMBO_EBUSY */
     uint32_t direct_below;    /* continuous policy: batches of fewer reads launch
                                  the plain kernel directly instead of replaying
-                                 the slot's graph (0: always replay) */
+                                 the slot's graph (0: always replay; 2049, the
+                                 Python binding's default, measured lowest
+                                 latency on MI355X at 1k-50k reads/s) */
 } rambo_server_config_t;
 
 typedef struct {

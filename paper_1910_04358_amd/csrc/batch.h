@@ -13,7 +13,7 @@ struct BatchBufs {
     uint64_t *extra;           // [cap] tiles beyond the first, per read
     uint64_t *extra_off;       // [cap + 1] exclusive scan of extra
     uint32_t *order;           // [4][cap] reads by size class of their first tile
-    unsigned long long *cls;   // [4] reads per size class
+    unsigned long long *cls;   // reads of size class v at cls[16 v]
     unsigned long long *head;  // queue position
     uint64_t cap;
 };

@@ -34,9 +34,11 @@ __device__ __forceinline__ uint64_t n_windows(uint64_t beg, uint64_t end) {
 // includes every multi-tile read). Order: class 3 first tiles, then every
 // extra tile (tiles 1.. of multi-tile reads; after their read's first tile,
 // which may empty the read's masks and let them skip), then classes 2, 1, 0.
+// (the four class counters are 128 bytes apart: their atomics use different
+// cache lines)
 __global__ void k_batch_reset(BatchBufs bb) {
     if (threadIdx.x == 0) *bb.head = 0;
-    if (threadIdx.x < 4) bb.cls[threadIdx.x] = 0;
+    if (threadIdx.x < 4) bb.cls[16 * threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t mw, uint32_t tile, BatchBufs bb) {
@@ -57,16 +59,29 @@ __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t
         }
         cls = (uint32_t)min<uint64_t>(3, min<uint64_t>(nw, tile) * 4 / tile);
     }
-    // one atomic per class and wave for the slots of the wave's reads
+    // slots in the class lists: ranks within the wave (ballots), wave
+    // offsets within the workgroup (LDS), one atomic per class and workgroup
+    __shared__ uint32_t wcount[4][4];  // [wave][class]
+    __shared__ unsigned long long bbase[4];
+    const uint32_t wave = threadIdx.x >> 6;
+    uint64_t mine = 0;
     for (uint32_t v = 0; v < 4; v++) {
         const uint64_t mask = __ballot(real && cls == v);
-        if (!mask) continue;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        unsigned long long base = 0;
-        if ((int)lane == leader) base = atomicAdd(bb.cls + v, (unsigned long long)__popcll(mask));
-        base = __shfl(base, leader);
-        if (real && cls == v)
-            bb.order[(uint64_t)v * bb.cap + base + __popcll(mask & ((1ULL << lane) - 1))] = (uint32_t)i;
+        if (cls == v) mine = mask;
+        if (lane == 0) wcount[wave][v] = (uint32_t)__popcll(mask);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const uint32_t v = threadIdx.x;
+        uint32_t tot = 0;
+        for (uint32_t k = 0; k < (blockDim.x >> 6); k++) tot += wcount[k][v];
+        bbase[v] = tot ? atomicAdd(bb.cls + 16 * v, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    if (real) {
+        uint64_t slot = bbase[cls] + __popcll(mine & ((1ULL << lane) - 1));
+        for (uint32_t k = 0; k < wave; k++) slot += wcount[k][cls];
+        bb.order[(uint64_t)cls * bb.cap + slot] = (uint32_t)i;
     }
 }
 
@@ -123,7 +138,7 @@ __global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in
     const uint64_t n = in->n;
     const uint64_t n_extra = bb.extra_off[n];
     const uint64_t total = n + n_extra;
-    const uint64_t c3 = uniform64(bb.cls[3]), c2 = uniform64(bb.cls[2]), c1 = uniform64(bb.cls[1]);
+    const uint64_t c3 = uniform64(bb.cls[48]), c2 = uniform64(bb.cls[32]), c1 = uniform64(bb.cls[16]);
     uint64_t issued = 0;
     for (;;) {
         uint64_t t0 = 0;
@@ -287,7 +302,7 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
         b_parts = al(scan_parts_needed(cap) * 8);
         b_order = al(4 * cap * 4);
     }
-    HIP_CHECK(hipMalloc(&bg.mem, b_mask + b_done + b_extra + b_off + b_parts + b_order + 512));
+    HIP_CHECK(hipMalloc(&bg.mem, b_mask + b_done + b_extra + b_off + b_parts + b_order + 640 + 256));
     char *p = (char *)bg.mem;
     bg.parts = (uint64_t *)p; p += b_parts;
     bg.bb.rmask = (uint32_t *)p; p += b_mask;
@@ -296,8 +311,8 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
     bg.bb.extra_off = (uint64_t *)p; p += b_off;
     bg.bb.order = (uint32_t *)p; p += b_order;
     bg.bb.head = (unsigned long long *)p;  // its own 128-byte line (every wave's queue atomic)
-    bg.bb.cls = bg.bb.head + 16;           // [4], the next line
-    p += 256;
+    bg.bb.cls = bg.bb.head + 16;           // class v at cls[16 v]: the next four lines
+    p += 640;
     bg.bb.cap = cap;
     if (in_dev) {
         bg.in = in_dev;

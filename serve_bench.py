@@ -16,7 +16,7 @@ RATES = (1000, 5000, 10000, 25000, 50000)
 
 
 def _serve(idx, reads, arrivals, policy, budget, slots=4, max_batch_reads=8192, max_batch_bytes=8 << 20,
-           direct_below=0):
+           direct_below=2049):
     from paper_1910_04358_amd import Server, clock
 
     n = reads.n
@@ -72,15 +72,19 @@ def run(idx, w, dev, log, rates=RATES, seconds=2.0, min_reads=2000, max_reads=10
         offs = torch.from_numpy(reads.offsets.view(np.int64)).to(dev)
         ref = idx.query_seqs(seqs, offs).cpu().numpy().view(np.uint64)
         rec = {"rate": lam, "reads": n}
-        for name, policy, direct in (("served", SERVE_CONTINUOUS, 0), ("served_direct_small", SERVE_CONTINUOUS, 2049),
+        # served: continuous batching, batches of up to 2048 reads launched
+        # directly, larger ones replayed from the slot's persistent graph;
+        # served_graph: every batch replayed from a graph; serial_plain: the
+        # one-batch-at-a-time baseline
+        for name, policy, direct in (("served", SERVE_CONTINUOUS, 2049), ("served_graph", SERVE_CONTINUOUS, 0),
                                      ("serial_plain", SERVE_SERIAL, 0)):
             m, bits = _serve(idx, reads, arrivals, policy, budget, direct_below=direct)
             if not np.array_equal(bits, ref):
                 raise SystemExit("served results differ from the plain kernel at rate %d (%s)" % (lam, name))
             rec[name] = m
-        log("serve %6d reads/s: served p50 %.3f p99 %.3f ms | direct-small p50 %.3f p99 %.3f | serial p50 %.3f "
+        log("serve %6d reads/s: served p50 %.3f p99 %.3f ms | graph-only p50 %.3f p99 %.3f | serial p50 %.3f "
             "p99 %.3f ms" % (lam, rec["served"]["p50_ms"], rec["served"]["p99_ms"],
-                             rec["served_direct_small"]["p50_ms"], rec["served_direct_small"]["p99_ms"],
+                             rec["served_graph"]["p50_ms"], rec["served_graph"]["p99_ms"],
                              rec["serial_plain"]["p50_ms"], rec["serial_plain"]["p99_ms"]))
         out["rates"].append(rec)
     return out

@@ -27,12 +27,16 @@ def collect(srv, n, timeout=30.0):
     return bits
 
 
-@pytest.mark.parametrize("policy", [rb.SERVE_CONTINUOUS, rb.SERVE_SERIAL])
-def test_served_results_equal_oracle(policy):
+@pytest.mark.parametrize("policy,direct_below", [(rb.SERVE_CONTINUOUS, 2049), (rb.SERVE_CONTINUOUS, 0),
+                                                 (rb.SERVE_SERIAL, 0)])
+def test_served_results_equal_oracle(policy, direct_below):
+    """Batches launched directly (small), replayed from the slot's plain-kernel
+    graph, and the serial baseline."""
     idx, o, dm, reads, want = setup_case("rw4")
     n = 1500
     arrivals = gen.poisson_arrivals(4100, 20_000.0, n)
-    srv = rb.Server(idx, budget_bytes=1 << 30, slots=3, max_batch_reads=256, max_batch_bytes=1 << 20, policy=policy)
+    srv = rb.Server(idx, budget_bytes=1 << 30, slots=3, max_batch_reads=256, max_batch_bytes=1 << 20, policy=policy,
+                    direct_below=direct_below)
     t0 = rb.clock() + 0.02
     offs = reads.offsets[: n + 1]
     srv.submit_schedule(reads.seqs[: int(offs[-1])], offs, t0 + arrivals)
@@ -43,6 +47,24 @@ def test_served_results_equal_oracle(policy):
         assert np.array_equal(bits[i], want[i]), i
     assert st["completed"] == n and st["batches"] >= 1
     assert st["max_batch_reads"] <= 256
+
+
+@pytest.mark.parametrize("direct_below", [0, 2049])
+def test_large_served_batches_use_the_persistent_form(direct_below):
+    """All reads arrive at once: batches above 2048 reads replay the slot's
+    persistent (batched-form) graph; results equal the oracle's."""
+    idx, o, dm, reads, want = setup_case("rw4")
+    n = reads.n
+    srv = rb.Server(idx, budget_bytes=1 << 30, slots=2, max_batch_reads=4096, max_batch_bytes=64 << 20,
+                    direct_below=direct_below)
+    t0 = rb.clock() + 0.05
+    srv.submit_schedule(reads.seqs, reads.offsets, np.full(n, t0))
+    bits = collect(srv, n)
+    st = srv.stats()
+    srv.stop()
+    for i in range(n):
+        assert np.array_equal(bits[i], want[i]), i
+    assert st["max_batch_reads"] > 2048, st
 
 
 def test_burst_alone_vs_mix_and_backpressure():
