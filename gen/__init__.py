@@ -55,8 +55,18 @@ def lib():
         L.gen_read_fill.argtypes = [u64, u64, u64, dbl, dbl, u64, u64, u64, dbl, i32, dbl, dbl, u64,
                                     u64, dbl, dbl, u64, u64, vp, vp, vp, vp, vp, vp, i32]
         L.gen_poisson_arrivals.argtypes = [u64, dbl, u64, vp]
+        L.gen_term_id.argtypes = [u64, u64]
+        L.gen_term_id.restype = u64
+        L.gen_term_doc_len.argtypes = [u64, u64, u64]
+        L.gen_term_doc_len.restype = u64
+        L.gen_zipf_cdf.argtypes = [u64, dbl, vp]
+        L.gen_term_docs.argtypes = [u64, u64, vp, u64, u64, vp, vp, i32]
+        L.gen_term_queries.argtypes = [u64, u64, vp, u64, u64, u64, dbl, u64, vp, vp, i32]
+        L.gen_term_phrase_lens.argtypes = [u64, u64, u64, u64, vp]
+        L.gen_term_phrases.argtypes = [u64, u64, vp, u64, u64, u64, dbl, u64, vp, vp, vp, i32]
         for f in ("gen_doc", "gen_docs", "gen_doc_window_codes", "gen_kmer_queries",
-                  "gen_read_offsets", "gen_read_fill", "gen_poisson_arrivals"):
+                  "gen_read_offsets", "gen_read_fill", "gen_poisson_arrivals", "gen_zipf_cdf",
+                  "gen_term_docs", "gen_term_queries", "gen_term_phrase_lens", "gen_term_phrases"):
             getattr(L, f).restype = None
         _lib = L
     return _lib
@@ -190,6 +200,96 @@ def poisson_arrivals(aseed: int, lam: float, n: int) -> np.ndarray:
     t = np.empty(n, dtype=np.float64)
     lib().gen_poisson_arrivals(aseed, lam, n, _ptr(t))
     return t
+
+
+# ---------------------------------------------------------------------------
+# Word-term documents (the web-document setting): a document is a set of
+# opaque 64-bit term ids (hashes of word unigrams), drawn from a Zipf
+# vocabulary; see gen.c.
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class TermDocModel:
+    seed: int
+    n_docs: int
+    mean_terms: int      # terms per document uniform in [mean/2, 3 mean/2]
+    vocab: int = 200_000
+    zipf_s: float = 1.0
+
+    def cdf(self) -> np.ndarray:
+        key = (self.vocab, self.zipf_s)
+        c = _CDF.get(key)
+        if c is None:
+            c = np.empty(self.vocab, dtype=np.float64)
+            lib().gen_zipf_cdf(self.vocab, self.zipf_s, _ptr(c))
+            _CDF[key] = c
+        return c
+
+    def doc_len(self, d: int) -> int:
+        return int(lib().gen_term_doc_len(self.seed, self.mean_terms, d))
+
+    def docs(self, d0: int = 0, nd: int | None = None):
+        """(terms uint64, offsets uint64[nd+1]) of documents d0 .. d0+nd-1."""
+        nd = self.n_docs - d0 if nd is None else nd
+        lens = np.array([self.doc_len(d0 + k) for k in range(nd)], dtype=np.uint64)
+        offs = np.zeros(nd + 1, dtype=np.uint64)
+        np.cumsum(lens, out=offs[1:])
+        out = np.empty(int(offs[-1]), dtype=np.uint64)
+        lib().gen_term_docs(self.seed, self.vocab, _ptr(self.cdf()), d0, nd, _ptr(offs), _ptr(out), nthreads())
+        return out, offs
+
+    def doc(self, d: int) -> np.ndarray:
+        return self.docs(d, 1)[0]
+
+    def term_queries(self, qseed: int, n: int, frac_present: float = 0.5):
+        out = np.empty(n, dtype=np.uint64)
+        src = np.empty(n, dtype=np.int64)
+        lib().gen_term_queries(self.seed, self.vocab, _ptr(self.cdf()), self.mean_terms, self.n_docs, qseed,
+                               frac_present, n, _ptr(out), _ptr(src), nthreads())
+        return out, src
+
+    def phrases(self, qseed: int, n: int, lo: int = 2, hi: int = 8, frac_doc: float = 0.5):
+        """n term-set queries: (terms, offsets[n+1], source doc or -1)."""
+        lens = np.empty(n, dtype=np.uint64)
+        lib().gen_term_phrase_lens(qseed, lo, hi, n, _ptr(lens))
+        offs = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(lens, out=offs[1:])
+        out = np.empty(int(offs[-1]), dtype=np.uint64)
+        src = np.empty(n, dtype=np.int64)
+        lib().gen_term_phrases(self.seed, self.vocab, _ptr(self.cdf()), self.mean_terms, self.n_docs, qseed,
+                               frac_doc, n, _ptr(offs), _ptr(out), _ptr(src), nthreads())
+        return out, offs, src
+
+
+_CDF: dict = {}
+
+
+@dataclass(frozen=True)
+class TermWorkload:
+    name: str
+    K: int
+    B: int
+    R: int
+    m: int
+    eta: int
+    docs: TermDocModel
+    index_seed: int
+    n_queries: int
+    qseed: int
+
+
+def term_workload(name: str) -> TermWorkload:
+    """The paper's two web-document index shapes (Section 6, document
+    indexing) on synthetic term sets: Wiki-dump-like (17,618 documents of
+    ~650 terms, B=1,000, R=2, 200,000-bit BFUs) and ClueWeb09-like (50,000
+    documents of ~450 terms, B=5,000, R=3, 20,000-bit BFUs); eta = 2."""
+    if name == "wiki":
+        dm = TermDocModel(seed=1101, n_docs=17_618, mean_terms=650, vocab=200_000)
+        return TermWorkload("wiki-K17618-B1000-R2-m200000", 17_618, 1000, 2, 200_000, 2, dm, 2101, 1_000_000, 3101)
+    if name == "clueweb":
+        dm = TermDocModel(seed=1102, n_docs=50_000, mean_terms=450, vocab=500_000)
+        return TermWorkload("clueweb-K50000-B5000-R3-m20000", 50_000, 5000, 3, 20_000, 2, dm, 2102, 1_000_000,
+                            3102)
+    raise ValueError(name)
 
 
 # ---------------------------------------------------------------------------

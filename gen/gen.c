@@ -301,3 +301,104 @@ void gen_poisson_arrivals(uint64_t aseed, double lam, uint64_t n, double *t_out)
         t_out[i] = t;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Word-term documents (the web-document setting: a document is a set of     */
+/* word unigrams). A vocabulary of V words with Zipf(s) frequencies, word w  */
+/* ranked w (0 most frequent); word w's term id is a 64-bit key of (seed, w), */
+/* standing for the hash of the token. Document d draws n_d words, n_d       */
+/* uniform in [mean/2, 3 mean/2], by inverse-CDF sampling of the Zipf law;  */
+/* term i of document d depends on (seed, d, i) only. Repeated words are     */
+/* kept (documents are sets downstream).                                     */
+/* ------------------------------------------------------------------------ */
+enum { TAG_TERM = 6, TAG_TDOC = 7, TAG_TQ = 8, TAG_TP = 9 };
+
+uint64_t gen_term_id(uint64_t seed, uint64_t w) { return key(seed, TAG_TERM, w); }
+
+uint64_t gen_term_doc_len(uint64_t seed, uint64_t mean, uint64_t d) {
+    uint64_t lo = mean / 2, span = mean + 1; /* [mean/2, mean/2 + mean] */
+    return lo + H(key(seed, TAG_TDOC, d), ~0ULL) % span;
+}
+
+/* cdf[w] = sum_{v <= w} (v+1)^-s / Z, w < V */
+void gen_zipf_cdf(uint64_t V, double s, double *cdf) {
+    double z = 0.0;
+    for (uint64_t w = 0; w < V; w++) z += pow((double)(w + 1), -s);
+    double acc = 0.0;
+    for (uint64_t w = 0; w < V; w++) {
+        acc += pow((double)(w + 1), -s) / z;
+        cdf[w] = acc;
+    }
+    cdf[V - 1] = 1.0;
+}
+
+static inline uint64_t zipf_draw(const double *cdf, uint64_t V, uint64_t v) {
+    double u = unit53(v);
+    uint64_t lo = 0, hi = V - 1; /* smallest w with cdf[w] > u */
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (cdf[mid] > u) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+static inline uint64_t term_of(uint64_t seed, const double *cdf, uint64_t V, uint64_t d, uint64_t i) {
+    return gen_term_id(seed, zipf_draw(cdf, V, H(key(seed, TAG_TDOC, d), i)));
+}
+
+/* documents d0 .. d0+nd-1: document d0+k's terms at out[offs[k] .. offs[k+1]) */
+void gen_term_docs(uint64_t seed, uint64_t V, const double *cdf, uint64_t d0, uint64_t nd, const uint64_t *offs,
+                   uint64_t *out, int nthreads) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t k = 0; k < (int64_t)nd; k++)
+        for (uint64_t i = 0; i < offs[k + 1] - offs[k]; i++) out[offs[k] + i] = term_of(seed, cdf, V, d0 + k, i);
+}
+
+/* single-term queries: a fraction present (a random term of a random
+ * document, source returned), the rest fresh random 64-bit values (-1) */
+void gen_term_queries(uint64_t seed, uint64_t V, const double *cdf, uint64_t mean, uint64_t n_docs,
+                      uint64_t qseed, double frac_present, uint64_t n, uint64_t *out, int64_t *src, int nthreads) {
+    uint64_t tp = thr53(frac_present);
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t q = 0; q < (int64_t)n; q++) {
+        uint64_t kq = key(qseed, TAG_TQ, (uint64_t)q);
+        if ((H(kq, 0) >> 11) < tp) {
+            uint64_t d = H(kq, 1) % n_docs, len = gen_term_doc_len(seed, mean, d);
+            out[q] = term_of(seed, cdf, V, d, H(kq, 2) % len);
+            if (src) src[q] = (int64_t)d;
+        } else {
+            out[q] = H(kq, 3);
+            if (src) src[q] = -1;
+        }
+    }
+}
+
+/* phrase queries (term sets): query q has len_q terms, len_q uniform in
+ * [lo, hi]; a fraction are consecutive terms of a random document (source
+ * returned), the rest terms of random documents mixed (source -1). Lengths
+ * first (gen_term_phrase_lens), then the terms at out[offs[q] ..]. */
+void gen_term_phrase_lens(uint64_t qseed, uint64_t lo, uint64_t hi, uint64_t n, uint64_t *lens) {
+    for (uint64_t q = 0; q < n; q++) lens[q] = lo + H(key(qseed, TAG_TP, q), 0) % (hi - lo + 1);
+}
+
+void gen_term_phrases(uint64_t seed, uint64_t V, const double *cdf, uint64_t mean, uint64_t n_docs, uint64_t qseed,
+                      double frac_doc, uint64_t n, const uint64_t *offs, uint64_t *out, int64_t *src, int nthreads) {
+    uint64_t tp = thr53(frac_doc);
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t q = 0; q < (int64_t)n; q++) {
+        uint64_t kq = key(qseed, TAG_TP, (uint64_t)q), len = offs[q + 1] - offs[q];
+        if ((H(kq, 1) >> 11) < tp) {
+            uint64_t d = H(kq, 2) % n_docs, dl = gen_term_doc_len(seed, mean, d);
+            uint64_t start = dl > len ? H(kq, 3) % (dl - len + 1) : 0;
+            for (uint64_t i = 0; i < len; i++) out[offs[q] + i] = term_of(seed, cdf, V, d, (start + i) % dl);
+            if (src) src[q] = (int64_t)d;
+        } else {
+            for (uint64_t i = 0; i < len; i++) {
+                uint64_t d = H(kq, 10 + 2 * i) % n_docs, dl = gen_term_doc_len(seed, mean, d);
+                out[offs[q] + i] = term_of(seed, cdf, V, d, H(kq, 11 + 2 * i) % dl);
+            }
+            if (src) src[q] = -1;
+        }
+    }
+}

@@ -67,6 +67,12 @@ def lib():
             "orc_query_kmers": ([vp, vp, u64, vp, i32, i32], None),
             "orc_query_seqs": ([vp, vp, vp, u64, vp, i32, i32, i32], u64),
             "orc_fold": ([vp], vp),
+            "orc_insert_terms": ([vp, u64, vp, u64], i32),
+            "orc_build_term_docs": ([vp, vp, vp, u64, u64, i32], i32),
+            "orc_query_termset_def": ([vp, vp, u64, vp], None),
+            "orc_query_termset_alg2": ([vp, vp, u64, vp, i32], u64),
+            "orc_query_terms": ([vp, vp, u64, vp, i32, i32], None),
+            "orc_query_termsets": ([vp, vp, vp, u64, vp, i32, i32, i32], u64),
         }
         for name, (a, r) in sig.items():
             f = getattr(L, name)
@@ -153,6 +159,44 @@ class Oracle:
         assert docs.size >= nd * doc_len
         if lib().orc_build_docs(self._h, _p(docs), doc_len, d0, nd, nthreads or _nthreads()) != 0:
             raise ValueError("document range exceeds K")
+
+    # -- opaque terms (word ids; no k-mer encoding)
+    def insert_terms(self, d: int, terms: np.ndarray) -> None:
+        t = np.ascontiguousarray(terms, dtype=np.uint64)
+        if lib().orc_insert_terms(self._h, d, _p(t), t.size) != 0:
+            raise ValueError("invalid document id")
+
+    def build_term_docs(self, terms: np.ndarray, offsets: np.ndarray, d0: int = 0, nthreads=None) -> None:
+        t = np.ascontiguousarray(terms, dtype=np.uint64)
+        o = np.ascontiguousarray(offsets, dtype=np.uint64)
+        if lib().orc_build_term_docs(self._h, _p(t), _p(o), d0, o.size - 1, nthreads or _nthreads()) != 0:
+            raise ValueError("document range exceeds K")
+
+    def query_terms(self, xs: np.ndarray, mode=MODE_DEF, nthreads=None) -> np.ndarray:
+        xs = np.ascontiguousarray(xs, dtype=np.uint64)
+        out = np.zeros((xs.size, self.W), dtype=np.uint64)
+        lib().orc_query_terms(self._h, _p(xs), xs.size, _p(out), mode, nthreads or _nthreads())
+        return out
+
+    def query_termset(self, terms, mode=MODE_DEF, early_exit=True) -> np.ndarray:
+        t = np.ascontiguousarray(terms, dtype=np.uint64)
+        out = np.zeros(self.W, dtype=np.uint64)
+        if mode == MODE_DEF:
+            lib().orc_query_termset_def(self._h, _p(t), t.size, _p(out))
+        else:
+            lib().orc_query_termset_alg2(self._h, _p(t), t.size, _p(out), int(early_exit))
+        return out
+
+    def query_termsets(self, terms: np.ndarray, offsets: np.ndarray, mode=MODE_ALG2, early_exit=True,
+                       nthreads=None):
+        """(results [n][W], single-term Bloom tests performed)."""
+        t = np.ascontiguousarray(terms, dtype=np.uint64)
+        o = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n = o.size - 1
+        out = np.zeros((n, self.W), dtype=np.uint64)
+        tests = lib().orc_query_termsets(self._h, _p(t), _p(o), n, _p(out), mode, int(early_exit),
+                                         nthreads or _nthreads())
+        return out, int(tests)
 
     # -- index contents
     def bits(self) -> np.ndarray:

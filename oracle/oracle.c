@@ -409,6 +409,76 @@ uint64_t orc_query_seqs(const orc_t *o, const uint8_t *seqs, const uint64_t *off
     return tests;
 }
 
+/* ---- opaque terms (document indexing with word terms, Section 6) --------- */
+/* Documents as sets of opaque 64-bit terms (word ids): Algorithm 1 and the
+ * queries of Section 3.3 with the terms taken as they are -- no k-mer
+ * encoding, any 64-bit value is a term. */
+int orc_insert_terms(orc_t *o, uint64_t d, const uint64_t *t, uint64_t n) {
+    if (d >= o->K) return -1;
+    for (uint32_t r = 0; r < o->R; r++) {
+        uint64_t *f = bfu(o, r, orc_phi(o, r, d));
+        for (uint64_t i = 0; i < n; i++) bf_insert(o, r, f, t[i]);
+    }
+    return 0;
+}
+
+/* documents d0 .. d0+nd-1 with terms t[offs[k] .. offs[k+1]); each thread
+ * owns whole BFUs (no two threads write one filter) */
+int orc_build_term_docs(orc_t *o, const uint64_t *t, const uint64_t *offs, uint64_t d0, uint64_t nd, int nthreads) {
+    if (d0 + nd > o->K) return -1;
+    int64_t cells = (int64_t)o->R * o->B;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t c = 0; c < cells; c++) {
+        uint32_t r = (uint32_t)(c / o->B), b = (uint32_t)(c % o->B);
+        uint64_t *f = bfu(o, r, b);
+        for (uint64_t k = 0; k < nd; k++) {
+            if (orc_phi(o, r, d0 + k) != b) continue;
+            for (uint64_t i = offs[k]; i < offs[k + 1]; i++) bf_insert(o, r, f, t[i]);
+        }
+    }
+    return 0;
+}
+
+/* Definition mode for a term set Q of n opaque terms (n = 1: one term):
+ * document d is reported iff every term passes the Bloom test of
+ * BFU(r, phi_r(d)) in every repetition r (Section 3.3, 3.3.1). */
+void orc_query_termset_def(const orc_t *o, const uint64_t *Q, uint64_t n, uint64_t *out) {
+    memset(out, 0, o->W * 8);
+    for (uint64_t d = 0; d < o->K; d++) {
+        int keep = 1;
+        for (uint64_t i = 0; i < n && keep; i++)
+            for (uint32_t r = 0; r < o->R && keep; r++) keep = bf_test(o, r, bfu(o, r, orc_phi(o, r, d)), Q[i]);
+        if (keep) setbit(out, d);
+    }
+}
+
+/* Algorithm 2 for a term set of opaque terms */
+uint64_t orc_query_termset_alg2(const orc_t *o, const uint64_t *Q, uint64_t n, uint64_t *out, int early_exit) {
+    return alg2(o, Q, n, out, early_exit);
+}
+
+/* batches: single terms, and term sets t[offs[i] .. offs[i+1]) */
+void orc_query_terms(const orc_t *o, const uint64_t *xs, uint64_t n, uint64_t *out, int mode, int nthreads) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; i++) {
+        if (mode == 0) orc_query_termset_def(o, xs + i, 1, out + (uint64_t)i * o->W);
+        else alg2(o, xs + i, 1, out + (uint64_t)i * o->W, 0);
+    }
+}
+
+uint64_t orc_query_termsets(const orc_t *o, const uint64_t *t, const uint64_t *offs, uint64_t n, uint64_t *out,
+                            int mode, int early_exit, int nthreads) {
+    uint64_t tests = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : tests) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; i++) {
+        const uint64_t *Q = t + offs[i];
+        uint64_t len = offs[i + 1] - offs[i];
+        if (mode == 0) orc_query_termset_def(o, Q, len, out + (uint64_t)i * o->W);
+        else tests += alg2(o, Q, len, out + (uint64_t)i * o->W, early_exit);
+    }
+    return tests;
+}
+
 /* ---- folding over (Section 5.3, Figure 3) -------------------------------- */
 /* BFU'(r, b) = BFU(r, b) OR BFU(r, b + B/2) for b < B/2; B must be even. The
  * folded index keeps R, m and the hash functions; a document's cell becomes

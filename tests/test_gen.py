@@ -106,3 +106,41 @@ def test_poisson_arrivals():
     gaps = np.diff(t)
     assert np.all(gaps > 0)
     assert abs(gaps.mean() - 1e-3) < 5e-5
+
+
+def test_term_documents_regenerate_and_have_their_shape():
+    dm = gen.TermDocModel(seed=3, n_docs=500, mean_terms=100, vocab=10_000)
+    terms, offs = dm.docs()
+    lens = np.diff(offs.astype(np.int64))
+    assert lens.min() >= 50 and lens.max() <= 150
+    for d in (0, 17, 499):
+        assert np.array_equal(dm.doc(d), terms[offs[d]:offs[d + 1]])
+    t2, o2 = dm.docs(200, 50)
+    assert np.array_equal(t2, terms[offs[200]:offs[250]])
+    # Zipf: the most frequent word is about 1/H_V of all draws
+    vals, counts = np.unique(terms, return_counts=True)
+    top = counts.max() / terms.size
+    hv = sum(1.0 / (k + 1) for k in range(10_000))
+    assert abs(top - 1 / hv) < 0.2 / hv
+    cdf = dm.cdf()
+    assert np.all(np.diff(cdf) > 0) and cdf[-1] == 1.0
+
+
+def test_term_queries_and_phrases_come_from_their_sources():
+    dm = gen.TermDocModel(seed=4, n_docs=200, mean_terms=60, vocab=5000)
+    terms, offs = dm.docs()
+    q, src = dm.term_queries(9, 1000, 0.5)
+    assert 400 < (src >= 0).sum() < 600
+    for i in np.nonzero(src >= 0)[0][:200]:
+        d = int(src[i])
+        assert q[i] in set(terms[offs[d]:offs[d + 1]].tolist())
+    pt, po, ps = dm.phrases(10, 300, 2, 6, 0.5)
+    lens = np.diff(po.astype(np.int64))
+    assert lens.min() >= 2 and lens.max() <= 6
+    for i in np.nonzero(ps >= 0)[0][:100]:
+        d = int(ps[i])
+        doc = terms[offs[d]:offs[d + 1]]
+        ph = pt[po[i]:po[i + 1]]
+        # consecutive terms of the document (cyclically)
+        starts = [s for s in range(doc.size) if doc[s] == ph[0]]
+        assert any(all(doc[(s + k) % doc.size] == ph[k] for k in range(ph.size)) for s in starts)

@@ -361,3 +361,105 @@ def test_fold_equals_rebuild_with_half_the_cells():
     s = dm.doc(7, 50, 80)
     assert np.array_equal(f.query_seq(s), half.query_seq(s))
     assert _ref.bits_to_ids(big.query_seq(s), K) <= _ref.bits_to_ids(f.query_seq(s), K)
+
+
+# ---------------------------------------------------------------- word terms
+# Document indexing with opaque word terms (Section 6): the same method with
+# the terms taken as they are.
+def _term_index(K, B, R, m, eta=2, seed=77, mean=40, vocab=2000, dseed=1201):
+    dm = gen.TermDocModel(seed=dseed, n_docs=K, mean_terms=mean, vocab=vocab)
+    terms, offs = dm.docs()
+    o = oracle.Oracle(K, B, R, m, eta, seed)
+    o.build_term_docs(terms, offs)
+    sets = [set(terms[offs[d]:offs[d + 1]].tolist()) for d in range(K)]
+    return dm, o, terms, offs, sets
+
+
+def test_terms_equal_kmers_on_canonical_codes():
+    """On canonical k-mer codes the term functions are the k-mer functions:
+    insertion of canonical codes as terms gives the same bits, and a term
+    query of canon(x) answers the k-mer query of x."""
+    dm = gen.DocModel(seed=9, n_docs=12, length=3000)
+    ok = oracle.Oracle(12, 4, 3, 1 << 16, 2, 31)
+    ot = oracle.Oracle(12, 4, 3, 1 << 16, 2, 31)
+    for d in range(12):
+        codes = dm.window_codes(d)
+        ok.insert_kmers(d, _ref.revcomp_np(codes) if d % 2 else codes)
+        ot.insert_terms(d, _ref.canon_np(codes))
+    assert np.array_equal(ok.bits(), ot.bits())
+    q, _ = gen.kmer_queries(dm, 5, 300, 0.5)
+    assert np.array_equal(ok.query_kmers(q), ot.query_terms(_ref.canon_np(q)))
+
+
+def test_terms_exact_partition_brute_force():
+    """Word-term documents with m far above the inserted terms (no Bloom
+    errors w.h.p.): single terms and term sets give RAMBO over exact sets
+    (d kept iff every term is in the union of d's cell in every repetition),
+    which contains the truth; Algorithm 2 equals the definition."""
+    K, B, R = 60, 7, 3
+    dm, o, terms, offs, sets = _term_index(K, B, R, 1 << 24)
+    phis = o.phis()
+    cell = {(r, b): set().union(*[sets[d] for d in range(K) if phis[r, d] == b]) for r in range(R) for b in range(B)}
+    q, src = dm.term_queries(11, 400, 0.5)
+    res = o.query_terms(q)
+    res2 = o.query_terms(q, oracle.MODE_ALG2)
+    assert np.array_equal(res, res2)
+    strict = 0
+    for i, x in enumerate(q.tolist()):
+        ex = {e for e in range(K) if all(x in cell[(r, phis[r, e])] for r in range(R))}
+        truth = {e for e in range(K) if x in sets[e]}
+        got = _ref.bits_to_ids(res[i], K)
+        assert truth <= ex and got == ex, i
+        if src[i] >= 0:
+            assert int(src[i]) in got
+        strict += ex != truth
+    assert strict > 0  # the partition does produce false positives here
+    pt, po, ps = dm.phrases(12, 200, 2, 6, 0.7)
+    got, _ = o.query_termsets(pt, po, oracle.MODE_ALG2, early_exit=True)
+    for i in range(200):
+        Q = set(pt[po[i]:po[i + 1]].tolist())
+        ex = {e for e in range(K) if all(Q <= cell[(r, phis[r, e])] for r in range(R))}
+        assert _ref.bits_to_ids(got[i], K) == ex, i
+        assert np.array_equal(o.query_termset(pt[po[i]:po[i + 1]], oracle.MODE_DEF), got[i])
+        if ps[i] >= 0:
+            assert int(ps[i]) in ex
+
+
+def test_term_sets_are_the_and_of_their_terms():
+    """Section 3.3.1 for term sets: the answer is the intersection of the
+    terms' answers, whatever their order; the empty set is every document."""
+    K = 300
+    dm, o, terms, offs, sets = _term_index(K, 20, 2, 1 << 12, mean=60, vocab=5000)
+    pt, po, ps = dm.phrases(13, 150, 1, 8, 0.6)
+    got, _ = o.query_termsets(pt, po)
+    single = o.query_terms(pt)
+    rng = np.random.default_rng(4)
+    for i in range(150):
+        a, b = int(po[i]), int(po[i + 1])
+        want = np.bitwise_and.reduce(single[a:b], axis=0)
+        assert np.array_equal(got[i], want), i
+        perm = pt[a:b][rng.permutation(b - a)]
+        assert np.array_equal(o.query_termset(perm, oracle.MODE_ALG2), want)
+    allk = o.query_termset(np.zeros(0, dtype=np.uint64), oracle.MODE_ALG2)
+    assert _ref.bits_to_ids(allk, K) == set(range(K))
+
+
+def test_terms_false_positive_law():
+    """Fresh terms on a loaded term index: document d is reported with
+    probability prod_r fill(r, phi_r(d))^eta (Section 2.1, independent
+    repetitions), about p^R on average (Lemma 4.1, V = 0)."""
+    K, B, R, m, eta = 400, 10, 2, 4096, 2
+    dm, o, terms, offs, sets = _term_index(K, B, R, m, eta=eta, mean=80, vocab=100_000)
+    phis = o.phis()
+    fill = np.array([[o.bfu_popcount(r, b) / m for b in range(B)] for r in range(R)])
+    pdoc = np.prod([fill[r, phis[r]] ** eta for r in range(R)], axis=0)
+    allterms = set(terms.tolist())
+    q, src = dm.term_queries(14, 4000, 0.0)
+    assert all(x not in allterms for x in q.tolist())
+    res = o.query_terms(q)
+    bits = np.unpackbits(res.view(np.uint8), axis=1, bitorder="little")[:, :K]
+    observed, expected = bits.sum(), q.size * pdoc.sum()
+    assert abs(observed - expected) < max(8 * math.sqrt(expected), 0.08 * expected), (observed, expected)
+    p = (fill ** eta).mean()
+    lemma = q.size * K * p ** R
+    assert abs(observed - lemma) < 0.2 * lemma, (observed, lemma)
