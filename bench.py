@@ -122,6 +122,53 @@ def kmer_queries_run(dev, steps, warmup):
     return rec
 
 
+def web_terms_run(dev, steps, warmup, n_sets=100_000):
+    """Document indexing with word terms (the paper's web-document setting)
+    on synthetic term sets shaped like its two samples: Wiki-dump-like
+    (17,618 documents of ~650 terms, B=1,000, R=2, m=200,000) and
+    ClueWeb09-like (50,000 documents of ~450 terms, B=5,000, R=3,
+    m=20,000); eta = 2. Build, 10^6 single-term queries (half present), and
+    term-set queries of 2-8 terms (half phrases of a document)."""
+    import torch
+    import gen
+    from paper_1910_04358_amd import Rambo
+
+    recs = {}
+    for name in ("wiki", "clueweb"):
+        w = gen.term_workload(name)
+        terms, offs = w.docs.docs()
+        idx = Rambo(w.K, w.B, w.R, w.m, w.eta, w.index_seed, opaque_terms=True)
+        ids, td, od = up(np.arange(w.K, dtype=np.uint64), dev), up(terms, dev), up(offs, dev)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        idx.insert_batch(ids, od, td)
+        e1.record()
+        torch.cuda.synchronize()
+        idx.sync()
+        build_ms = e0.elapsed_time(e1)
+        q, _ = w.docs.term_queries(w.qseed, w.n_queries, 0.5)
+        qd = up(q, dev)
+        out = torch.empty((q.size, idx.W), dtype=torch.int64, device=dev)
+        ms = time_steps(lambda: idx.query_kmers(qd, out=out), steps, warmup)
+        pt, po, _ = w.docs.phrases(w.qseed + 1, n_sets, 2, 8, 0.5)
+        ptd, pod = up(pt, dev), up(po, dev)
+        out2 = torch.empty((n_sets, idx.W), dtype=torch.int64, device=dev)
+        ms2 = time_steps(lambda: idx.query_term_sets(ptd, pod, out=out2, check=False), steps, warmup)
+        recs[name] = {"workload": w.name, "terms_indexed": int(terms.size), "build_ms": build_ms,
+                      "build_terms_per_s": terms.size / build_ms * 1e3, "index_bytes": idx.index_bytes,
+                      "queries": int(q.size), "ms_per_batch": ms, "term_queries_per_s": q.size / ms * 1e3,
+                      "out_GBps": q.size * idx.W * 8 / ms / 1e6, "term_sets": n_sets,
+                      "ms_per_set_batch": ms2, "term_sets_per_s": n_sets / ms2 * 1e3}
+        log("terms %s: build %.1f ms (%.3g terms/s); %.3g term queries/s (%.0f GB/s of results); %.3g term sets/s"
+            % (w.name, build_ms, recs[name]["build_terms_per_s"], recs[name]["term_queries_per_s"],
+               recs[name]["out_GBps"], recs[name]["term_sets_per_s"]))
+        idx.close()
+        del out, out2, qd, td, od, ptd, pod
+        torch.cuda.empty_cache()
+    return recs
+
+
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -191,6 +238,7 @@ def main():
     ap.add_argument("--tune", default=None,
                     help="batched launch shape seg,tile,waves_per_cu,wpb,grab (skips the autotuner)")
     ap.add_argument("--no-kmers", action="store_true", help="skip the single k-mer query workload")
+    ap.add_argument("--no-terms", action="store_true", help="skip the word-term (web document) workloads")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a 1 GiB device copy (scale for hardware byte counters)")
     ap.add_argument("--only", choices=["plain", "batched"], default=None,
@@ -299,6 +347,10 @@ def main():
         ms = micro.copy(1 << 30)
         log("copy kernel: 1 GiB in %.3f ms" % ms)
 
+    web = None
+    if not args.no_terms:
+        web = web_terms_run(dev, min(args.steps, 10), min(args.warmup, 2))
+
     kq = None
     if not args.no_kmers:
         kq = kmer_queries_run(dev, args.steps, args.warmup)
@@ -348,6 +400,7 @@ def main():
         "cpu_baseline": cpu,
         "served": served,
         "kmer_queries": kq,
+        "web_terms": web,
     }
     if not args.no_fold and args.only is None:
         # folding over (B -> B/2, streaming), then the same batch on the folded index

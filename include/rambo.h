@@ -96,6 +96,19 @@ enum {
  * its device memory. */
 rambo_t *rambo_create(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed);
 
+enum { RAMBO_TERMS_OPAQUE = 1 };
+
+/* As rambo_create, with flags. RAMBO_TERMS_OPAQUE: an index of documents
+ * given as sets of opaque 64-bit terms (word ids; the document indexing of
+ * Section 6) instead of 31-mers: rambo_insert, rambo_insert_batch,
+ * rambo_query_kmers and rambo_query_term_sets take the values as they are
+ * (no k-mer encoding, no range check: every 64-bit value is a term), and the
+ * sequence entry points (rambo_insert_seqs, rambo_query_seqs,
+ * rambo_query_seqs_ids, rambo_server_start) return RAMBO_EINVAL. Unknown
+ * flags: RAMBO_EINVAL. */
+rambo_t *rambo_create_ex(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed,
+                         uint32_t flags);
+
 /* Free the index and everything the handle owns. NULL-safe. Waits for the
  * handle's own outstanding work. */
 void rambo_destroy(rambo_t *h);
@@ -196,6 +209,20 @@ int rambo_query_kmers(rambo_t *h, const uint64_t *kmers, uint64_t n, uint64_t *o
 int rambo_query_seqs(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
                      uint64_t *out, void *stream);
 
+/* Term-set queries (Section 3.3.1 for a query given as its terms, e.g. a
+ * phrase of words): query i is terms[offsets[i] .. offsets[i+1]) and its
+ * answer is the documents that hold every term: per repetition the AND of
+ * the terms' positive-BFU masks, then the per-document AND over repetitions
+ * (Algorithm 2). On a k-mer index the values are 2-bit 31-mer codes of either
+ * strand; a query holding a value >= 4^31 answers no document and is counted
+ * as invalid (reported by rambo_sync). On an opaque-term index any value is a
+ * term. An empty set answers every document. Device arrays (offsets n + 1
+ * words, non-decreasing; out n * W words as rambo_query_kmers), asynchronous
+ * on `stream`; one wave per set, repetition 0 over all terms before the
+ * others; the resolve and early exit settings apply. */
+int rambo_query_term_sets(rambo_t *h, const uint64_t *terms, const uint64_t *offsets, uint64_t n, uint64_t *out,
+                          void *stream);
+
 /* As rambo_query_seqs, but results are ascending document-id lists: read i's
  * ids are ids[id_offsets[i] .. id_offsets[i+1]) (device arrays, id_offsets
  * has n+1 entries, ids has room for ids_cap entries). Uses `scratch` (device,
@@ -282,6 +309,10 @@ typedef struct {
                                  the slot's graph (0: always replay; 2049, the
                                  Python binding's default, measured lowest
                                  latency on MI355X at 1k-50k reads/s) */
+    uint32_t batch_wait_us;   /* batching window: a batch smaller than
+                                 max_batch_reads is held until its oldest read
+                                 has been pending this long (0: never held,
+                                 the lowest latency) */
 } rambo_server_config_t;
 
 typedef struct {

@@ -121,6 +121,15 @@ RAMBO_API const char *rambo_last_error(void) { return g_err.c_str(); }
 RAMBO_API int rambo_last_status(void) { return g_status; }
 
 RAMBO_API rambo_t *rambo_create(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed) {
+    return rambo_create_ex(K, B, R, m, eta, seed, 0);
+}
+
+RAMBO_API rambo_t *rambo_create_ex(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed,
+                                   uint32_t flags) {
+    if (flags & ~(uint32_t)RAMBO_TERMS_OPAQUE) {
+        fail(RAMBO_EINVAL, "rambo_create_ex: unknown flags 0x%x", flags);
+        return nullptr;
+    }
     if (K == 0 || K >= (1ULL << 32) || B == 0 || B > RAMBO_MAX_B || R == 0 || R > RAMBO_MAX_R || eta == 0 ||
         eta > RAMBO_MAX_ETA || m == 0 || m > (1ULL << 40)) {
         fail(RAMBO_EINVAL, "rambo_create: parameters out of range (K=%llu B=%u R=%u m=%llu eta=%u)",
@@ -129,6 +138,7 @@ RAMBO_API rambo_t *rambo_create(uint64_t K, uint32_t B, uint32_t R, uint64_t m, 
     }
     auto *h = new rambo_s();
     h->K = K; h->B = B; h->R = R; h->m = m; h->eta = eta; h->seed = seed;
+    h->opaque = (flags & RAMBO_TERMS_OPAQUE) != 0;
     uint32_t need = (B + 31) / 32, rw = 1, lg = 0;
     while (rw < need) { rw <<= 1; lg++; }
     h->RW = rw;
@@ -294,7 +304,7 @@ RAMBO_API int rambo_insert(rambo_t *h, uint64_t doc_id, const uint64_t *kmers, u
     if (doc_id >= h->K) return fail(RAMBO_EINVAL, "rambo_insert: doc_id %llu >= K", (unsigned long long)doc_id);
     if (n == 0) return RAMBO_OK;
     if (!kmers) return fail(RAMBO_EINVAL, "rambo_insert: null k-mer array");
-    for (uint64_t i = 0; i < n; i++)
+    for (uint64_t i = 0; i < n && !h->opaque; i++)
         if (kmers[i] >> 62)
             return fail(RAMBO_EINVAL, "rambo_insert: value %llu at %llu is not a 31-mer code",
                         (unsigned long long)kmers[i], (unsigned long long)i);
@@ -324,6 +334,7 @@ RAMBO_API int rambo_insert_seqs(rambo_t *h, const uint64_t *doc_ids, const uint8
     if (!h) return fail(RAMBO_EINVAL, "rambo_insert_seqs: null handle");
     if (n_docs == 0) return RAMBO_OK;
     if (!doc_ids || !seqs || !offsets) return fail(RAMBO_EINVAL, "rambo_insert_seqs: null array");
+    if (h->opaque) return fail(RAMBO_EINVAL, "rambo_insert_seqs: the index holds opaque terms, not 31-mers");
     return launch_build_seqs(h, seqs, offsets, doc_ids, n_docs, (hipStream_t)stream);
 }
 
@@ -342,8 +353,17 @@ RAMBO_API int rambo_query_seqs(rambo_t *h, const uint8_t *seqs, const uint64_t *
     if (!h) return fail(RAMBO_EINVAL, "rambo_query_seqs: null handle");
     if (n == 0) return RAMBO_OK;
     if (!seqs || !offsets || !out) return fail(RAMBO_EINVAL, "rambo_query_seqs: null array");
+    if (h->opaque) return fail(RAMBO_EINVAL, "rambo_query_seqs: the index holds opaque terms, not 31-mers");
     if (h->mode == RAMBO_MODE_BATCHED) return query_seqs_batched(h, seqs, offsets, n, out, (hipStream_t)stream);
     return launch_query_seqs_plain(h, seqs, offsets, n, out, (hipStream_t)stream, default_seg(h->RW));
+}
+
+RAMBO_API int rambo_query_term_sets(rambo_t *h, const uint64_t *terms, const uint64_t *offsets, uint64_t n,
+                                    uint64_t *out, void *stream) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_query_term_sets: null handle");
+    if (n == 0) return RAMBO_OK;
+    if (!terms || !offsets || !out) return fail(RAMBO_EINVAL, "rambo_query_term_sets: null array");
+    return launch_query_termsets(h, terms, offsets, n, out, (hipStream_t)stream);
 }
 
 RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
@@ -351,6 +371,7 @@ RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64
                                    void *stream) {
     if (!h) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null handle");
     if (!id_offsets) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null id_offsets");
+    if (h->opaque) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: the index holds opaque terms, not 31-mers");
     if (n > 0 && (!scratch || !seqs || !offsets)) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null array");
     if (n > 0) {
         int st = rambo_query_seqs(h, seqs, offsets, n, scratch, stream);

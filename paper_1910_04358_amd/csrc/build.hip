@@ -46,11 +46,11 @@ __global__ __launch_bounds__(256) void k_build_kmers(Index ix, const uint64_t *_
     for (uint64_t i = first + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < last; i += stride) {
         const uint64_t k = find_doc(koff, n_docs, i);
         const uint64_t d = doc_ids[k], x = kmers[i];
-        if (d >= ix.K || (x >> 62)) {
+        if (d >= ix.K || (!ix.opaque && (x >> 62))) {
             atomicAdd(invalid, 1ULL);
             continue;
         }
-        scatter_term(ix, canonical(x), d);
+        scatter_term(ix, ix.opaque ? x : canonical(x), d);
     }
 }
 

@@ -36,14 +36,14 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
     set_ones(acc);
     if (q < n) {
         const uint64_t x = kmers[q];
-        if (x >> 62) {
+        if (!ix.opaque && (x >> 62)) {
             if (seg == 0) atomicAdd(invalid, 1ULL);
 #pragma unroll
             for (int r = 0; r < MAXR; r++)
 #pragma unroll
                 for (int s = 0; s < SEG; s++) acc[r].w[s] = 0;
         } else {
-            probe_and<SEG>(ix, canonical(x), seg, acc);
+            probe_and<SEG>(ix, ix.opaque ? x : canonical(x), seg, acc);
         }
     }
     // stage every term's masks; alive = no repetition mask is empty
@@ -198,6 +198,80 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
     resolve(ix, M, res, o, lane, opt.rmode);
 }
 
+// -------------------------------------------------------------------------
+// term-set queries: one wave per set, 64 terms per step; repetition 0 over
+// every term first, then the other repetitions (Section 3.3.1 order)
+// -------------------------------------------------------------------------
+template <int SEG, int G>
+__global__ __launch_bounds__(256) void k_query_termsets(Index ix, const uint64_t *__restrict__ terms,
+                                                        const uint64_t *__restrict__ offs, uint64_t n,
+                                                        uint64_t *__restrict__ out, QueryOpts opt, int use_res,
+                                                        unsigned long long *invalid) {
+    extern __shared__ __align__(16) uint64_t smem64[];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const WaveLds L = wave_lds(ix.R * ix.RW, ix.W, use_res != 0, false);
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * L.total;
+    uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + L.res) : nullptr;
+
+    const uint64_t q = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (q >= n) return;
+    const uint64_t beg = offs[q];
+    uint64_t end = offs[q + 1];
+    if (end < beg) end = beg;
+    const uint64_t len = end - beg;
+    uint64_t *o = out + q * ix.W;
+
+    // a k-mer index takes 31-mer codes only: a set holding another value
+    // answers no document
+    bool bad = false;
+    if (!ix.opaque)
+        for (uint64_t w = 0; w < len && !bad; w += 64)
+            bad = __ballot(w + lane < len && (terms[beg + w + lane] >> 62)) != 0;
+    if (bad) {
+        if (lane == 0) atomicAdd(invalid, 1ULL);
+        write_zeros(o, ix.W, lane);
+        return;
+    }
+    init_masks(ix, M, lane);
+    uint64_t issued = 0;
+    bool ended = false;
+    for (int pass = 0; pass < 2 && !ended; pass++) {
+        if (pass == 1 && ix.R == 1) break;
+        for (uint64_t w = 0; w < len; w += 64) {
+            const bool valid = w + lane < len;
+            const uint64_t x = valid ? terms[beg + w + lane] : 0;
+            Window wv;
+            wv.canon = ix.opaque ? x : canonical(x);
+            wv.valid = valid;
+            const uint64_t nv = (uint64_t)__popcll(__ballot(valid));
+            bool alive;
+            if (pass == 0) {
+                alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid, lane, M);
+                issued += nv;
+            } else {
+                alive = probe_group<SEG, G, 1, 4>(ix, step_params(ix), wv, valid, lane, M);
+                issued += nv * (min(ix.R, 5u) - 1);
+                if ((int)ix.R > 5 && (alive || !opt.early_exit)) {
+                    alive &= probe_group<SEG, G, 5, MAXR - 5>(ix, step_params(ix), wv, valid, lane, M);
+                    issued += nv * (ix.R - 5);
+                }
+            }
+            if (opt.early_exit && !alive) {
+                ended = true;
+                break;
+            }
+        }
+    }
+    if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (masks_some_rep_empty(ix, M, lane)) {
+        write_zeros(o, ix.W, lane);
+        return;
+    }
+    resolve(ix, M, res, o, lane, opt.rmode);
+}
+
 static constexpr uint32_t kMaxLds = 64 * 1024;
 
 int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *out, hipStream_t s) {
@@ -242,6 +316,29 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
                        n, hdr, out, opt, use_res)
+    RAMBO_DISPATCH_SPLIT(seg, G)
+#undef RAMBO_SPLIT_BODY_
+    HIP_CHECK(hipGetLastError());
+    return RAMBO_OK;
+}
+
+int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *offs, uint64_t n, uint64_t *out,
+                          hipStream_t s) {
+    const Index ix = make_index(h);
+    const int seg = default_seg(h->RW), G = (int)h->RW / seg;
+    const int WPB = 4;
+    int use_res = 1;
+    size_t lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, true, false).total * 4;
+    if (lds > kMaxLds) {
+        use_res = 0;
+        lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, false, false).total * 4;
+    }
+    const uint64_t blocks = (n + WPB - 1) / WPB;
+    if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_term_sets: batch too large");
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, SCHED_SWEEP};
+#define RAMBO_SPLIT_BODY_                                                                                  \
+    hipLaunchKernelGGL((k_query_termsets<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, terms, offs, \
+                       n, out, opt, use_res, h->d_invalid)
     RAMBO_DISPATCH_SPLIT(seg, G)
 #undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());

@@ -37,6 +37,7 @@ struct Index {
     uint64_t K;
     uint32_t B, R, eta, RW;  // RW = 32-bit words per row (power of two)
     uint32_t log2RW, W;      // W = result words per query
+    uint32_t opaque;         // terms are opaque 64-bit values (no k-mer encoding)
 };
 
 // phi_r(d) from document d's cell record

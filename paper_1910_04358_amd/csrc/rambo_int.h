@@ -48,6 +48,7 @@ struct rambo_s {
     uint32_t B = 0, R = 0, eta = 0, RW = 0, log2RW = 0;
     int device = 0, n_cu = 0;
     uint64_t rows_bytes = 0;
+    bool opaque = false;  // documents are sets of opaque 64-bit terms
     uint32_t *rows = nullptr;
     rambo::HashParams *d_hp = nullptr;
     uint4 *d_cells = nullptr;  // [K] phi_r(d) of every repetition, 16 bits each
@@ -82,6 +83,7 @@ inline Index make_index(const rambo_s *h) {
     ix.RW = h->RW;
     ix.log2RW = h->log2RW;
     ix.W = (uint32_t)h->W;
+    ix.opaque = h->opaque ? 1u : 0u;
     return ix;
 }
 
@@ -105,6 +107,8 @@ int launch_fold(rambo_s *h, const uint32_t *in, uint32_t *out, uint32_t RWi, uin
 int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *out, hipStream_t s);
 // With hdr (device), the batch is read from it on the device and n is only
 // the capacity the grid is sized for.
+int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *offs, uint64_t n, uint64_t *out,
+                          hipStream_t s);
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
                             uint64_t *out, hipStream_t s, int seg, const InputHdr *hdr = nullptr);
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off,

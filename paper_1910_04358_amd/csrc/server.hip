@@ -35,6 +35,7 @@ struct Request {
     uint64_t tag;
     double t_arrival;
     std::shared_ptr<std::vector<uint8_t>> own;  // single submissions own their bytes
+    double t_pending = 0;                       // entered the pending queue (rambo_clock)
 };
 
 // A slot's staging area (pinned on the host, mirrored on the device) holds
@@ -154,6 +155,16 @@ static void dispatcher_main(rambo_server_s *s) {
             });
             if (s->stopping && (s->pending.empty() || s->error != RAMBO_OK)) return;
             if (s->pending.empty() || s->free_slots.empty()) continue;
+            // batching window: a partial batch waits until it fills or its
+            // oldest read has been pending batch_wait_us
+            if (s->cfg.batch_wait_us && !s->stopping && s->pending.size() < s->cfg.max_batch_reads) {
+                const double due = s->pending.front().t_pending + s->cfg.batch_wait_us * 1e-6;
+                const double d = due - now_s();
+                if (d > 0) {
+                    s->cv_dispatch.wait_for(lk, std::chrono::duration<double>(std::min(d, 1e-3)));
+                    continue;
+                }
+            }
             slot = s->free_slots.front();
             s->free_slots.pop_front();
             Slot &sl = s->slots[slot];
@@ -262,6 +273,7 @@ static int enqueue_request(rambo_server_s *s, Request r) {
             s->stats.rejected++;
             return fail(RAMBO_EBUSY, "server queue full (%u pending)", s->cfg.queue_cap);
         }
+        r.t_pending = now_s();
         s->pending.push_back(std::move(r));
         s->stats.submitted++;
     }
@@ -333,6 +345,10 @@ using namespace rambo;
 RAMBO_API double rambo_clock(void) { return now_s(); }
 
 RAMBO_API rambo_server_t *rambo_server_start(rambo_t *h, const rambo_server_config_t *cfg) {
+    if (h && h->opaque) {
+        fail(RAMBO_EINVAL, "rambo_server_start: the index holds opaque terms, not 31-mers");
+        return nullptr;
+    }
     if (!h || !cfg || cfg->slots == 0 || cfg->slots > 64 || cfg->max_batch_reads == 0 || cfg->max_batch_bytes == 0 ||
         cfg->budget_bytes == 0 || cfg->queue_cap == 0 ||
         (cfg->policy != RAMBO_SERVE_CONTINUOUS && cfg->policy != RAMBO_SERVE_SERIAL)) {

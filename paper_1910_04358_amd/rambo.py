@@ -21,6 +21,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EDEVICE, ETRUNC, EBUSY = 0, -1, -2, -3, -4, -5
 MODE_PLAIN, MODE_BATCHED = 0, 1
 RESOLVE_AUTO, RESOLVE_DENSE, RESOLVE_CANDIDATE = 0, 1, 2
+TERMS_OPAQUE = 1
 MAX_R, MAX_ETA, MAX_B = 8, 8, 8192
 
 # every function the C ABI exports, with its ctypes signature
@@ -39,6 +40,8 @@ class TuneC(ctypes.Structure):
 
 SIGNATURES = {
     "rambo_create": ([_u64, _u32, _u32, _u64, _u32, _u64], _vp),
+    "rambo_create_ex": ([_u64, _u32, _u32, _u64, _u32, _u64, _u32], _vp),
+    "rambo_query_term_sets": ([_vp, _vp, _vp, _u64, _vp, _vp], _i32),
     "rambo_destroy": ([_vp], None),
     "rambo_last_error": ([], _cp),
     "rambo_last_status": ([], _i32),
@@ -79,7 +82,7 @@ SERVE_CONTINUOUS, SERVE_SERIAL = 0, 1
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", _u64), ("slots", _u32), ("max_batch_reads", _u32), ("max_batch_bytes", _u64),
-                ("policy", _u32), ("queue_cap", _u32), ("direct_below", _u32)]
+                ("policy", _u32), ("queue_cap", _u32), ("direct_below", _u32), ("batch_wait_us", _u32)]
 
 
 class Completion(ctypes.Structure):
@@ -160,9 +163,12 @@ class Tune:
 class Rambo:
     """A RAMBO index resident on the current GPU."""
 
-    def __init__(self, K: int, B: int, R: int, m: int, eta: int, seed: int):
+    def __init__(self, K: int, B: int, R: int, m: int, eta: int, seed: int, opaque_terms: bool = False):
+        """opaque_terms: documents are sets of opaque 64-bit terms (word ids)
+        instead of 31-mers; see rambo_create_ex."""
         L = lib()
-        self._h = L.rambo_create(K, B, R, m, eta, seed)
+        self.opaque_terms = bool(opaque_terms)
+        self._h = L.rambo_create_ex(K, B, R, m, eta, seed, TERMS_OPAQUE if opaque_terms else 0)
         if not self._h:
             raise RamboError(L.rambo_last_status(), L.rambo_last_error().decode(errors="replace"))
         lay = self.layout()
@@ -267,6 +273,24 @@ class Rambo:
                                            _stream(stream)))
         return out
 
+    def query_term_sets(self, terms, offsets, out=None, stream=None, check=True):
+        """Term-set queries: set i is terms[offsets[i] .. offsets[i+1])
+        (device int64 tensors); returns out [n][W]."""
+        import torch
+        n = offsets.numel() - 1
+        if check:
+            check_offsets(offsets, terms.numel())
+        if out is None:
+            out = torch.empty((max(n, 0), self.W), dtype=torch.int64, device=offsets.device)
+        if out.numel() < n * self.W:
+            raise ValueError("out too small")
+        if n > 0:
+            if terms.numel() == 0:
+                terms = torch.zeros(1, dtype=torch.int64, device=offsets.device)
+            _check(lib().rambo_query_term_sets(self._h, _dptr(terms, "terms", _i64()), _dptr(offsets, "offsets", _i64()),
+                                               n, _dptr(out, "out", _i64()), _stream(stream)))
+        return out
+
     def query_seqs(self, seqs, offsets, out=None, stream=None, check=True):
         import torch
         n = offsets.numel() - 1
@@ -351,9 +375,11 @@ class Server:
     """Continuous-batching server over a resident index (RAMBO_SERVE_*)."""
 
     def __init__(self, idx: "Rambo", budget_bytes=4 << 30, slots=4, max_batch_reads=8192,
-                 max_batch_bytes=8 << 20, policy=SERVE_CONTINUOUS, queue_cap=1 << 20, direct_below=2049):
+                 max_batch_bytes=8 << 20, policy=SERVE_CONTINUOUS, queue_cap=1 << 20, direct_below=2049,
+                 batch_wait_us=0):
         self.idx = idx
-        cfg = ServerConfig(budget_bytes, slots, max_batch_reads, max_batch_bytes, policy, queue_cap, direct_below)
+        cfg = ServerConfig(budget_bytes, slots, max_batch_reads, max_batch_bytes, policy, queue_cap, direct_below,
+                           batch_wait_us)
         self._s = lib().rambo_server_start(idx._h, ctypes.byref(cfg))
         if not self._s:
             raise RamboError(lib().rambo_last_status(), lib().rambo_last_error().decode(errors="replace"))

@@ -51,12 +51,13 @@ def test_served_results_equal_oracle(policy, direct_below):
 
 @pytest.mark.parametrize("direct_below", [0, 2049])
 def test_large_served_batches_use_the_persistent_form(direct_below):
-    """All reads arrive at once: batches above 2048 reads replay the slot's
+    """All reads arrive at once and a 200 ms batching window holds the batch
+    until it is complete: one batch of all 3,000 reads replays the slot's
     persistent (batched-form) graph; results equal the oracle's."""
     idx, o, dm, reads, want = setup_case("rw4")
     n = reads.n
-    srv = rb.Server(idx, budget_bytes=1 << 30, slots=2, max_batch_reads=4096, max_batch_bytes=64 << 20,
-                    direct_below=direct_below)
+    srv = rb.Server(idx, budget_bytes=1 << 30, slots=2, max_batch_reads=n, max_batch_bytes=64 << 20,
+                    direct_below=direct_below, batch_wait_us=200_000)
     t0 = rb.clock() + 0.05
     srv.submit_schedule(reads.seqs, reads.offsets, np.full(n, t0))
     bits = collect(srv, n)
@@ -65,6 +66,7 @@ def test_large_served_batches_use_the_persistent_form(direct_below):
     for i in range(n):
         assert np.array_equal(bits[i], want[i]), i
     assert st["max_batch_reads"] > 2048, st
+    assert st["batches"] <= 2, st
 
 
 def test_burst_alone_vs_mix_and_backpressure():
