@@ -199,3 +199,31 @@ def test_k101000_streaming_and_id_lists_full():
         lst = ids[id_off[i]:id_off[i + 1]]
         assert int(reads.src[i]) in set(lst.tolist())
     idx.close()
+
+
+@pytest.mark.parametrize("name", ["wiki", "clueweb"])
+def test_web_term_workloads_full(name):
+    """The two web-document term indexes at their full size (51-61 MB, which
+    the oracle builds whole): every BFU bit, 20,000 single-term queries and
+    5,000 term sets bit-exact; present terms and phrases find their source."""
+    w = gen.term_workload(name)
+    terms, offs = w.docs.docs()
+    idx = rb.Rambo(w.K, w.B, w.R, w.m, w.eta, w.index_seed, opaque_terms=True)
+    idx.insert_batch(to_dev(np.arange(w.K, dtype=np.uint64)), to_dev(offs), to_dev(terms))
+    idx.sync()
+    o = oracle.Oracle(w.K, w.B, w.R, w.m, w.eta, w.index_seed)
+    o.build_term_docs(terms, offs)
+    assert np.array_equal(idx.bfu_major(), o.bits())
+    q, src = w.docs.term_queries(w.qseed, 20_000, 0.5)
+    want = o.query_terms(q, oracle.MODE_ALG2)
+    got = to_host_u64(idx.query_kmers(to_dev(q)))
+    assert np.array_equal(got, want)
+    for i in np.nonzero(src >= 0)[0]:
+        assert bit_of(got[i:i + 1], int(src[i]))[0]
+    pt, po, ps = w.docs.phrases(w.qseed + 1, 5000, 2, 8, 0.5)
+    want2, _ = o.query_termsets(pt, po, oracle.MODE_ALG2, early_exit=True)
+    got2 = to_host_u64(idx.query_term_sets(to_dev(pt), to_dev(po)))
+    assert np.array_equal(got2, want2)
+    for i in np.nonzero(ps >= 0)[0]:
+        assert bit_of(got2[i:i + 1], int(ps[i]))[0]
+    idx.close()
