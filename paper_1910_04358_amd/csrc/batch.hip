@@ -458,8 +458,9 @@ static int time_candidate(rambo_s *h, const Tune &tu, const uint8_t *seqs, const
     HIP_CHECK(hipEventCreate(&a));
     HIP_CHECK(hipEventCreate(&b));
     int st = run_graph(h, tu, seqs, offs, n, out, s);  // warm-up (and graph build)
+    if (st == RAMBO_OK) st = run_graph(h, tu, seqs, offs, n, out, s);
     float best = 1e30f;
-    for (int rep = 0; rep < 3 && st == RAMBO_OK; rep++) {
+    for (int rep = 0; rep < 5 && st == RAMBO_OK; rep++) {
         (void)hipEventRecord(a, s);
         st = run_graph(h, tu, seqs, offs, n, out, s);
         (void)hipEventRecord(b, s);
@@ -501,12 +502,28 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
         }
         return RAMBO_OK;
     };
-    for (int tile : {128, 256, 512, 2048}) { Tune t = best; t.tile = tile; if ((st = consider(t))) return st; }
-    for (int wpc : {8, 12, 24, 32}) { Tune t = best; t.waves_per_cu = wpc; if ((st = consider(t))) return st; }
-    for (int seg : {1, 2, 4}) { Tune t = best; t.seg = seg; if (t.seg != best.seg && (st = consider(t))) return st; }
-    for (int grab : {2, 4, 16}) { Tune t = best; t.grab = grab; if ((st = consider(t))) return st; }
-    for (int wpb : {1, 2}) { Tune t = best; t.wpb = wpb; if ((st = consider(t))) return st; }
-    for (int sched : {0, 1, 2}) { Tune t = best; t.sched = sched; if (sched != best.sched && (st = consider(t))) return st; }
+    // two rounds of coordinate search (the second revisits every axis from
+    // the first round's shape); a candidate must beat the best by 2 %
+    for (int round = 0; round < 2; round++) {
+        for (int tile : {128, 256, 512, 1024, 2048, 4096}) {
+            Tune t = best; t.tile = tile;
+            if (t.tile != best.tile && (st = consider(t))) return st;
+        }
+        for (int wpc : {8, 12, 16, 20, 24, 32}) {
+            Tune t = best; t.waves_per_cu = wpc;
+            if (t.waves_per_cu != best.waves_per_cu && (st = consider(t))) return st;
+        }
+        for (int seg : {1, 2, 4}) { Tune t = best; t.seg = seg; if (t.seg != best.seg && (st = consider(t))) return st; }
+        for (int grab : {1, 2, 4, 16}) {
+            Tune t = best; t.grab = grab;
+            if (t.grab != best.grab && (st = consider(t))) return st;
+        }
+        for (int wpb : {1, 2, 4}) { Tune t = best; t.wpb = wpb; if (t.wpb != best.wpb && (st = consider(t))) return st; }
+        for (int sched : {0, 1, 2}) {
+            Tune t = best; t.sched = sched;
+            if (sched != best.sched && (st = consider(t))) return st;
+        }
+    }
     std::lock_guard<std::mutex> g(h->mu);
     h->tune = best;
     drop_graphs(h);  // keep only graphs of the chosen shape
