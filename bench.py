@@ -122,6 +122,52 @@ def kmer_queries_run(dev, steps, warmup):
     return rec
 
 
+def k101000_run(dev, steps, warmup):
+    """One GPU's share of a cluster-scale index: K = 101,000 capacity, 1,000
+    ancestors x 100 mutants of 100 kbp (1 %), R=6, B=1,000, m=2^27, eta=2
+    (96 GiB); build of 100,000 documents (10^10 k-mers), then 10^6 reads of
+    U(100, 1000) bp (70 % from documents with 1 % errors), batched form,
+    answered as bitsets and as document-id lists."""
+    import torch
+    import gen
+    from paper_1910_04358_amd import MODE_BATCHED, MODE_PLAIN
+
+    w = gen.workload(5)
+    idx, build_ms, build_kmers = build_index(w, dev, docs_per_chunk=2000)
+    reads = gen.reads(w.docs, w.reads, w.n_reads)
+    n_kmers = reads.n_windows()
+    seqs, offs = up(reads.seqs, dev), up(reads.offsets, dev)
+    out = torch.empty((reads.n, idx.W), dtype=torch.int64, device=dev)
+
+    def step():
+        idx.query_seqs(seqs, offs, out=out, check=False)
+
+    idx.set_mode(MODE_PLAIN)
+    plain_ms = time_steps(step, steps, warmup)
+    idx.set_mode(MODE_BATCHED)
+    step()  # autotune
+    ms = time_steps(step, steps, warmup)
+    probes = torch.zeros(1, dtype=torch.int64, device=dev)
+    idx.set_probe_counter(probes)
+    step()
+    torch.cuda.synchronize()
+    issued = int(probes.item())
+    idx.set_probe_counter(None)
+    ids_ms = time_steps(lambda: idx.query_seqs_ids(seqs, offs, ids_cap=50_000_000, scratch=out), 3, 1)
+    rec = {"workload": w.name, "index_bytes": idx.index_bytes, "build_ms": build_ms,
+           "build_input_GBps_u64_kmers": build_kmers * 8 / build_ms / 1e6, "reads": reads.n, "kmers": n_kmers,
+           "plain_ms": plain_ms, "batched_ms": ms, "kmer_per_s": n_kmers / ms * 1e3, "reads_per_s": reads.n / ms * 1e3,
+           "probes": issued, "row_bytes": idx.row_words * 4, "rows_per_s": issued / ms * 1e3,
+           "ids_ms": ids_ms, "tune": idx.get_tune().__dict__}
+    log("K101000: build %.0f ms (%.3g k-mer/s); plain %.2f ms, batched %.2f ms per 10^6 reads (%.3g k-mer/s, %.3g rows "
+        "of %d B/s); as id lists %.2f ms" % (build_ms, build_kmers / build_ms * 1e3, plain_ms, ms, rec["kmer_per_s"],
+                                            rec["rows_per_s"], rec["row_bytes"], ids_ms))
+    idx.close()
+    del out, seqs, offs
+    torch.cuda.empty_cache()
+    return rec
+
+
 def web_terms_run(dev, steps, warmup, n_sets=100_000):
     """Document indexing with word terms (the paper's web-document setting)
     on synthetic term sets shaped like its two samples: Wiki-dump-like
@@ -239,6 +285,7 @@ def main():
                     help="batched launch shape seg,tile,waves_per_cu,wpb,grab (skips the autotuner)")
     ap.add_argument("--no-kmers", action="store_true", help="skip the single k-mer query workload")
     ap.add_argument("--no-terms", action="store_true", help="skip the word-term (web document) workloads")
+    ap.add_argument("--no-k101000", action="store_true", help="skip the K=101,000 (96 GiB) workload")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a 1 GiB device copy (scale for hardware byte counters)")
     ap.add_argument("--only", choices=["plain", "batched"], default=None,
@@ -418,8 +465,13 @@ def main():
                         "note": "wall time of the synchronous call (allocation + kernel + table rebuild)"}
         log("fold: B %d -> %d in %.1f ms (%.0f GB/s incl. allocation); plain step after: %.3f ms"
             % (w.B, idx.B, fold_s * 1e3, moved / fold_s / 1e9, folded_ms))
-    print(json.dumps(line), flush=True)
     idx.close()
+    del seqs, offs, out
+    torch.cuda.empty_cache()
+    line["k101000"] = None
+    if not args.no_k101000 and args.only is None:
+        line["k101000"] = k101000_run(dev, min(args.steps, 5), min(args.warmup, 1))
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

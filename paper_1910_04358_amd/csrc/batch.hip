@@ -121,8 +121,10 @@ __device__ __forceinline__ bool read_dead(const Index &ix, const uint32_t *rm, u
     return dead;
 }
 
+// Rows split over G > 1 lanes: the compiler's default would take 172 VGPRs
+// (2 waves per SIMD); 3 waves fit without spilling.
 template <int SEG, int G>
-__global__ __launch_bounds__(256) void k_batch_main(Index ix, const InputHdr *in, uint64_t *__restrict__ out,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 : 3))) void k_batch_main(Index ix, const InputHdr *in, uint64_t *__restrict__ out,
                                                     BatchBufs bb, QueryOpts opt, int use_res, uint32_t tile,
                                                     uint32_t grab) {
     const uint8_t *__restrict__ seqs = in->seqs;

@@ -308,6 +308,30 @@ __device__ __forceinline__ void probe_reps(const Index &ix, const HashRec *hp, u
     }
 }
 
+// Rows of U terms (this lane's segment seg) in repetition r, ETA hashes each:
+// all U * ETA loads are issued before any is used. A term with !v[u] loads
+// row 0 instead (in range, its value unused) so that no branch separates the
+// loads; the result for it is not ANDed.
+template <int SEG, int U, int ETA>
+__device__ __forceinline__ void probe_terms_eta(const Index &ix, const HashRec *hp, int r, const uint64_t (&x)[U],
+                                                const bool (&v)[U], uint32_t seg, Seg<SEG> &cm) {
+    Seg<SEG> rows[U][ETA];
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int j = 0; j < ETA; j++) {
+            const uint64_t pos = v[u] ? bloom_pos(hp[r * ETA + j], ix.m, x[u]) : 0;
+            rows[u][j] = load_seg<SEG>(row_ptr(ix, r, pos) + seg * SEG);
+        }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+        if (v[u])
+#pragma unroll
+            for (int j = 0; j < ETA; j++)
+#pragma unroll
+                for (int s = 0; s < SEG; s++) cm.w[s] &= rows[u][j].w[s];
+}
+
 // The hash parameter table, re-derived at every step of a probe loop: the
 // compiler then reloads a group's parameters (one scalar load per hash) at
 // each step instead of hoisting every repetition's parameters out of the
@@ -383,14 +407,36 @@ __device__ __forceinline__ bool probe_group(const Index &ix, const HashRec *hp, 
         if (valid) probe_reps<SEG, FIRST, COUNT>(ix, hp, wv.canon, 0, cm);
     } else {
         // the lanes of a term group split the row: the group's term comes
-        // from the lane that extracted it
+        // from the lane that extracted it (64/G terms per sub-step, G
+        // sub-steps per step)
         constexpr int KPW = 64 / G;
+        constexpr int U = (G >= 4) ? 4 : G;  // sub-steps whose loads go together
+        if (COUNT == 1 && (ix.eta == 1 || ix.eta == 2)) {
+            // one repetition, the rows of U sub-steps in flight together
 #pragma unroll 1
-        for (int sub = 0; sub < G; sub++) {
-            const int src = sub * KPW + (int)(lane / G);
-            const uint64_t x = __shfl(wv.canon, src);
-            const int v = __shfl((int)valid, src);
-            if (v) probe_reps<SEG, FIRST, COUNT>(ix, hp, x, lane % G, cm);
+            for (int s0 = 0; s0 < G; s0 += U) {
+                uint64_t xs[U];
+                bool vs[U];
+                bool any = false;
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const int src = (s0 + u) * KPW + (int)(lane / G);
+                    xs[u] = __shfl(wv.canon, src);
+                    vs[u] = __shfl((int)valid, src) != 0;
+                    any |= vs[u];
+                }
+                if (__ballot(any) == 0) continue;  // no term in these sub-steps
+                if (ix.eta == 2) probe_terms_eta<SEG, U, 2>(ix, hp, FIRST, xs, vs, lane % G, cm[0]);
+                else probe_terms_eta<SEG, U, 1>(ix, hp, FIRST, xs, vs, lane % G, cm[0]);
+            }
+        } else {
+#pragma unroll 1
+            for (int sub = 0; sub < G; sub++) {
+                const int src = sub * KPW + (int)(lane / G);
+                const uint64_t x = __shfl(wv.canon, src);
+                const int v = __shfl((int)valid, src);
+                if (v) probe_reps<SEG, FIRST, COUNT>(ix, hp, x, lane % G, cm);
+            }
         }
     }
     bool alive = true;
