@@ -68,6 +68,35 @@ __global__ __launch_bounds__(256) void k_gather4(const uint32_t *__restrict__ bu
     if (acc == 0x12345678u) sink[gid & 1023] = acc;
 }
 
+// Rows of ROWB bytes read cooperatively, as the probe kernel reads rows wider
+// than 16 bytes: ROWB/16 consecutive lanes each load one 16-byte piece of the
+// same random row; U rows in flight per lane group.
+template <int ROWB, int U>
+__global__ __launch_bounds__(256) void k_gather_coop(const uint4 *__restrict__ buf, uint64_t n_rows, uint32_t iters,
+                                                     uint64_t seed, uint4 *sink) {
+    constexpr int LPR = ROWB / 16;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t grp = gid / LPR;
+    const uint32_t piece = threadIdx.x % LPR;
+    uint64_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) x[u] = mix64(seed ^ (grp * U + u + 1));
+    uint4 acc = {0, 0, 0, 0};
+    for (uint32_t it = 0; it < iters; it++) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            v[u] = buf[__umul64hi(x[u], n_rows) * LPR + piece];
+            x[u] = mix64(x[u] + 0x9E3779B97F4A7C15ULL);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            acc.x ^= v[u].x; acc.y ^= v[u].y; acc.z ^= v[u].z; acc.w ^= v[u].w;
+        }
+    }
+    if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x12345678u) sink[gid & 1023] = acc;
+}
+
 // random single-bit atomic ORs into 32-bit words
 __global__ __launch_bounds__(256) void k_atomic_or(uint32_t *buf, uint64_t n_words, uint32_t iters, uint64_t seed) {
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,7 +129,9 @@ MICRO_API double micro_copy(void *dst, const void *src, uint64_t bytes, uint32_t
 }
 
 // Returns the kernel time in ms (events), or a negative value on error.
-// kind: 0 = gather, 1 = atomic OR. row_bytes: 4, 16, 64 or 128.
+// kind: 0 = gather (one lane per row), 1 = atomic OR, 2 = cooperative gather
+// (row_bytes/16 lanes per row). row_bytes: 4, 16, 64 or 128 (kind 0); 32, 64,
+// 128 or 256 (kind 2).
 MICRO_API double micro_run(int kind, void *buf, uint64_t bytes, int row_bytes, uint32_t blocks, uint32_t iters,
                            uint64_t seed, void *sink) {
     hipEvent_t a, b;
@@ -108,6 +139,15 @@ MICRO_API double micro_run(int kind, void *buf, uint64_t bytes, int row_bytes, u
     hipEventRecord(a, 0);
     if (kind == 1) {
         hipLaunchKernelGGL(k_atomic_or, dim3(blocks), dim3(256), 0, 0, (uint32_t *)buf, bytes / 4, iters, seed);
+    } else if (kind == 2) {
+        const uint64_t rows = bytes / (uint64_t)row_bytes;
+        switch (row_bytes) {
+        case 32: hipLaunchKernelGGL((k_gather_coop<32, 4>), dim3(blocks), dim3(256), 0, 0, (const uint4 *)buf, rows, iters, seed, (uint4 *)sink); break;
+        case 64: hipLaunchKernelGGL((k_gather_coop<64, 4>), dim3(blocks), dim3(256), 0, 0, (const uint4 *)buf, rows, iters, seed, (uint4 *)sink); break;
+        case 128: hipLaunchKernelGGL((k_gather_coop<128, 4>), dim3(blocks), dim3(256), 0, 0, (const uint4 *)buf, rows, iters, seed, (uint4 *)sink); break;
+        case 256: hipLaunchKernelGGL((k_gather_coop<256, 4>), dim3(blocks), dim3(256), 0, 0, (const uint4 *)buf, rows, iters, seed, (uint4 *)sink); break;
+        default: return -2;
+        }
     } else {
         const uint64_t rows = bytes / (uint64_t)row_bytes;
         switch (row_bytes) {
@@ -129,8 +169,10 @@ MICRO_API double micro_run(int kind, void *buf, uint64_t bytes, int row_bytes, u
 }
 
 // loads (or atomics) each lane issues per call, for throughput accounting
+// (kind 2: one row per row_bytes/16 lanes per load)
 MICRO_API uint32_t micro_per_lane(int kind, int row_bytes) {
     if (kind == 1) return 1;
+    if (kind == 2) return 4;
     switch (row_bytes) {
     case 4: return 8;
     case 16: return 8;

@@ -44,7 +44,7 @@ def copy(nbytes: int = 1 << 30) -> float:
     return ms
 
 
-def run(sizes_gib, rows, iters=16, reps=3, atomics=True):
+def run(sizes_gib, rows, iters=16, reps=3, atomics=True, coop_rows=(32, 64, 128, 256)):
     import torch
     L = lib()
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
@@ -54,7 +54,7 @@ def run(sizes_gib, rows, iters=16, reps=3, atomics=True):
     for gib in sizes_gib:
         nbytes = int(gib * (1 << 30))
         buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        cases = [(0, rb) for rb in rows] + ([(1, 4)] if atomics else [])
+        cases = [(0, rb) for rb in rows] + [(2, rb) for rb in coop_rows] + ([(1, 4)] if atomics else [])
         for kind, rb in cases:
             best = None
             for rep in range(reps):
@@ -64,9 +64,11 @@ def run(sizes_gib, rows, iters=16, reps=3, atomics=True):
                     raise RuntimeError("micro_run failed (%g)" % ms)
                 best = ms if best is None else min(best, ms)
             n = blocks * 256 * iters * L.micro_per_lane(kind, rb)
-            rec = {"kind": "gather" if kind == 0 else "atomic_or", "buffer_GiB": gib, "row_bytes": rb,
+            if kind == 2:
+                n //= rb // 16  # rows: rb/16 lanes share one
+            rec = {"kind": ("gather", "atomic_or", "coop_gather")[kind], "buffer_GiB": gib, "row_bytes": rb,
                    "ops": n, "ms": best, "ops_per_s": n / best * 1e3,
-                   "useful_GBps": n * rb / best / 1e6, "GBps_at_64B": n * max(64, rb) / best / 1e6}
+                   "useful_GBps": n * rb / best / 1e6, "line_GBps_at_128B": n * max(128, rb) / best / 1e6}
             print(json.dumps(rec), flush=True)
             out.append(rec)
         del buf
@@ -78,9 +80,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes-gib", default="1,8,40,96")
     ap.add_argument("--rows", default="4,16,64,128")
+    ap.add_argument("--coop-rows", default="32,64,128,256")
     ap.add_argument("--iters", type=int, default=16)
     a = ap.parse_args()
-    run([float(s) for s in a.sizes_gib.split(",")], [int(r) for r in a.rows.split(",")], iters=a.iters)
+    run([float(s) for s in a.sizes_gib.split(",")], [int(r) for r in a.rows.split(",")], iters=a.iters,
+        coop_rows=[int(r) for r in a.coop_rows.split(",") if r])
 
 
 if __name__ == "__main__":
