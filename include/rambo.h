@@ -226,9 +226,13 @@ int rambo_query_term_sets(rambo_t *h, const uint64_t *terms, const uint64_t *off
 /* As rambo_query_seqs, but results are ascending document-id lists: read i's
  * ids are ids[id_offsets[i] .. id_offsets[i+1]) (device arrays, id_offsets
  * has n+1 entries, ids has room for ids_cap entries). Uses `scratch` (device,
- * n * W words) for the bitsets. Synchronous on `stream` (it must learn the
- * total). If the total exceeds ids_cap, returns RAMBO_ETRUNC with
- * id_offsets filled (id_offsets[n] = required capacity) and ids untouched. */
+ * n * W words) for the bitsets of non-empty answers: rows of reads with no id
+ * are not written (their contents are unspecified afterwards), which spares
+ * the bitset traffic of the many empty answers. Synchronous on `stream` (it
+ * must learn the total). If the total exceeds ids_cap, returns RAMBO_ETRUNC
+ * with id_offsets filled (id_offsets[n] = required capacity) and ids
+ * untouched. Calls on one handle are serialised (a per-handle buffer holds
+ * the answer sizes). */
 int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
                          uint64_t *scratch, uint32_t *ids, uint64_t *id_offsets, uint64_t ids_cap,
                          void *stream);

@@ -184,8 +184,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
             __builtin_amdgcn_wave_barrier();
             if (ntiles == 1) {
                 // the whole read was in this tile: resolve from its masks
-                if (masks_some_rep_empty(ix, M, lane)) write_zeros(o, ix.W, lane);
-                else resolve(ix, M, res, o, lane, opt.rmode);
+                answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, i);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 continue;
@@ -214,8 +213,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
                     M[w] = __hip_atomic_fetch_or(rm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                if (masks_some_rep_empty(ix, M, lane)) write_zeros(o, ix.W, lane);
-                else resolve(ix, M, res, o, lane, opt.rmode);
+                answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, i);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
@@ -237,7 +235,8 @@ static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, hipStream_t 
     return launch_exclusive_scan(bg.bb.extra, &bg.in->n, bg.cap, bg.bb.extra_off, bg.parts, s);
 }
 
-static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *out, hipStream_t s) {
+static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *out, hipStream_t s,
+                        unsigned long long *counts) {
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
     const int G = (int)h->RW / tu.seg;
@@ -248,7 +247,7 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
         use_res = 0;
         lds = (size_t)tu.wpb * wave_lds(mw, h->W, false, stage).total * 4;
     }
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched, counts};
     // a persistent grid must be resident: never more workgroups than fit
 #define RAMBO_SPLIT_BODY_                                                                                  \
     {                                                                                                      \
@@ -332,7 +331,7 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
 }
 
 int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const InputHdr *init, uint64_t cap,
-                     uint64_t *out, std::shared_ptr<BatchGraph> &res) {
+                     uint64_t *out, std::shared_ptr<BatchGraph> &res, unsigned long long *counts) {
     auto bg = std::make_shared<BatchGraph>();
     bg->cap = cap;
     bg->tune = tu;
@@ -341,7 +340,7 @@ int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const I
         st = capture(h, &bg->graph_prep, &bg->exec_prep, [&](hipStream_t s) { return enqueue_prep(h, tu, *bg, s); });
     if (st == RAMBO_OK)
         st = capture(h, &bg->graph_main, &bg->exec_main,
-                     [&](hipStream_t s) { return enqueue_main(h, tu, *bg, out, s); });
+                     [&](hipStream_t s) { return enqueue_main(h, tu, *bg, out, s, counts); });
     if (st != RAMBO_OK) return st;
     res = bg;
     return RAMBO_OK;
@@ -371,25 +370,27 @@ int launch_batch_graph(rambo_s *h, BatchGraph &bg, hipStream_t s) {
     return RAMBO_OK;
 }
 
-static std::string graph_key(const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out) {
+static std::string graph_key(const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
+                             const unsigned long long *counts) {
     char buf[256];
-    snprintf(buf, sizeof buf, "%p/%p/%llu/%p/%d.%d.%d.%d.%d.%d", (const void *)seqs, (const void *)offs,
-             (unsigned long long)n, (void *)out, tu.seg, tu.tile, tu.waves_per_cu, tu.wpb, tu.grab, tu.sched);
+    snprintf(buf, sizeof buf, "%p/%p/%llu/%p/%p/%d.%d.%d.%d.%d.%d", (const void *)seqs, (const void *)offs,
+             (unsigned long long)n, (void *)out, (const void *)counts, tu.seg, tu.tile, tu.waves_per_cu, tu.wpb,
+             tu.grab, tu.sched);
     return buf;
 }
 
 static int run_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
-                     uint64_t *out, hipStream_t s) {
+                     uint64_t *out, hipStream_t s, unsigned long long *counts = nullptr) {
     std::shared_ptr<BatchGraph> bg;
     std::lock_guard<std::mutex> g(h->mu);
-    const std::string key = graph_key(tu, seqs, offs, n, out);
+    const std::string key = graph_key(tu, seqs, offs, n, out, counts);
     auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         bg = it->second;
     } else {
         if (h->graphs.size() >= 16) h->graphs.clear();
         const InputHdr init{n, offs, seqs, 0};
-        int st = make_batch_graph(h, tu, nullptr, &init, n, out, bg);
+        int st = make_batch_graph(h, tu, nullptr, &init, n, out, bg, counts);
         if (st != RAMBO_OK) return st;
         h->graphs[key] = bg;
     }
@@ -533,7 +534,7 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
 }
 
 int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                       hipStream_t s) {
+                       hipStream_t s, unsigned long long *counts) {
     if (!h->tuned) {
         h->tune.seg = default_seg(h->RW);
         const char *mode = getenv("RAMBO_TUNE");
@@ -550,7 +551,7 @@ int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, ui
         std::lock_guard<std::mutex> g(h->mu);
         tu = h->tune;
     }
-    return run_graph(h, tu, seqs, offs, n, out, s);
+    return run_graph(h, tu, seqs, offs, n, out, s, counts);
 }
 
 }  // namespace rambo

@@ -191,11 +191,7 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
     uint64_t *o = out + read * ix.W;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (masks_some_rep_empty(ix, M, lane)) {
-        write_zeros(o, ix.W, lane);
-        return;
-    }
-    resolve(ix, M, res, o, lane, opt.rmode);
+    answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, read);
 }
 
 // -------------------------------------------------------------------------
@@ -298,7 +294,7 @@ int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *
 }
 
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                            hipStream_t s, int seg, const InputHdr *hdr) {
+                            hipStream_t s, int seg, const InputHdr *hdr, unsigned long long *counts) {
     // with hdr, the batch is read on the device and n is only its capacity
     const Index ix = make_index(h);
     const int G = (int)h->RW / seg;
@@ -312,7 +308,7 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     }
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, h->tune.sched};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, h->tune.sched, counts};
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
                        n, hdr, out, opt, use_res)
@@ -335,7 +331,7 @@ int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *off
     }
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_term_sets: batch too large");
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, SCHED_SWEEP};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, SCHED_SWEEP, nullptr};
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_termsets<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, terms, offs, \
                        n, out, opt, use_res, h->d_invalid)
@@ -366,6 +362,7 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ bi
     const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (i >= n) return;
     uint64_t base = off[i];
+    if (off[i + 1] == base) return;  // no id: the bitset need not be read again
     for (uint32_t w0 = 0; w0 < W; w0 += 64) {
         const uint32_t w = w0 + lane;
         uint64_t word = w < W ? bits[i * W + w] : 0;
@@ -387,7 +384,7 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ bi
 }
 
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off, uint64_t ids_cap,
-               hipStream_t s) {
+               hipStream_t s, const unsigned long long *given) {
     const uint32_t W = (uint32_t)h->W;
     uint64_t total = 0;
     if (n == 0) {
@@ -402,7 +399,8 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
     const uint64_t n_host = n;
     HIP_CHECK(hipMemcpyAsync(d_n, &n_host, 8, hipMemcpyHostToDevice, s));
     const unsigned blocks = (unsigned)((n + 3) / 4);
-    hipLaunchKernelGGL(k_count_bits, dim3(blocks), dim3(256), 0, s, bits, n, W, counts);
+    if (given) HIP_CHECK(hipMemcpyAsync(counts, given, n * 8, hipMemcpyDeviceToDevice, s));
+    else hipLaunchKernelGGL(k_count_bits, dim3(blocks), dim3(256), 0, s, bits, n, W, counts);
     int sst = launch_exclusive_scan(counts, d_n, n, id_off, parts, s);
     if (sst != RAMBO_OK) {
         (void)hipFreeAsync(counts, s);

@@ -644,8 +644,9 @@ __device__ __forceinline__ bool doc_kept(const Index &ix, const uint32_t *M, con
 // Dense: every document tests its R cells; lane l handles document 64 w + l
 // and a ballot forms result word w. Four words' cell records are loaded
 // together.
-__device__ __forceinline__ void resolve_dense(const Index &ix, const uint32_t *M, uint64_t *out, uint32_t lane) {
+__device__ __forceinline__ uint64_t resolve_dense(const Index &ix, const uint32_t *M, uint64_t *out, uint32_t lane) {
     constexpr uint32_t U = 4;
+    uint64_t pc = 0;  // this lane's documents kept
     for (uint32_t w0 = 0; w0 < ix.W; w0 += 64) {
         uint64_t mine = 0;
         const uint32_t nw = min(64u, ix.W - w0);
@@ -664,8 +665,12 @@ __device__ __forceinline__ void resolve_dense(const Index &ix, const uint32_t *M
                 if (lane == t + u) mine = word;
             }
         }
-        if (lane < nw) out[w0 + lane] = mine;
+        if (lane < nw) {
+            out[w0 + lane] = mine;
+            pc += (uint64_t)__popcll(mine);
+        }
     }
+    return pc;
 }
 
 // Candidate: only documents of positive repetition-0 cells can survive the
@@ -676,8 +681,8 @@ __device__ __forceinline__ void resolve_dense(const Index &ix, const uint32_t *M
 // each lane then tests candidates k = lane, lane + 64, ... -- the cell range
 // loads, the document ids and their cell records each take one round trip
 // for up to 128 candidates.
-__device__ __forceinline__ void resolve_candidates(const Index &ix, const uint32_t *M, uint64_t *res,
-                                                   uint64_t *out, uint32_t lane) {
+__device__ __forceinline__ uint64_t resolve_candidates(const Index &ix, const uint32_t *M, uint64_t *res,
+                                                       uint64_t *out, uint32_t lane) {
     for (uint32_t w = lane; w < ix.W; w += 64) res[w] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -728,7 +733,13 @@ __device__ __forceinline__ void resolve_candidates(const Index &ix, const uint32
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t w = lane; w < ix.W; w += 64) out[w] = res[w];
+    uint64_t pc = 0;
+    for (uint32_t w = lane; w < ix.W; w += 64) {
+        const uint64_t v = res[w];
+        out[w] = v;
+        pc += (uint64_t)__popcll(v);
+    }
+    return pc;
 }
 
 // Number of candidates of the repetition-0 cells set in M, estimated from the
@@ -739,20 +750,41 @@ __device__ __forceinline__ uint64_t estimate_candidates(const Index &ix, const u
     return cells * ((ix.K + ix.B - 1) / ix.B);
 }
 
-// resolve: 0 auto, 1 dense, 2 candidate (res == nullptr forces dense)
-__device__ __forceinline__ void resolve(const Index &ix, const uint32_t *M, uint64_t *res, uint64_t *out,
-                                        uint32_t lane, int mode) {
+// resolve: 0 auto, 1 dense, 2 candidate (res == nullptr forces dense).
+// Returns the number of documents reported (wave-uniform).
+__device__ __forceinline__ uint64_t resolve(const Index &ix, const uint32_t *M, uint64_t *res, uint64_t *out,
+                                            uint32_t lane, int mode) {
     bool cand = false;
     if (res != nullptr) {
         if (mode == 2) cand = true;
         else if (mode == 0) cand = estimate_candidates(ix, M) * (ix.R - 1) * 2 < ix.K * ix.R;
     }
-    if (cand) resolve_candidates(ix, M, res, out, lane);
-    else resolve_dense(ix, M, out, lane);
+    uint64_t pc = cand ? resolve_candidates(ix, M, res, out, lane) : resolve_dense(ix, M, out, lane);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off);
+    return pc;
 }
+
 
 __device__ __forceinline__ void write_zeros(uint64_t *out, uint32_t W, uint32_t lane) {
     for (uint32_t w = lane; w < W; w += 64) out[w] = 0;
+}
+
+// Answer of a read whose masks are final: with counts (id-list mode) an
+// empty answer writes only its count (the bitset row is left as it is) and
+// a non-empty one its bitset and count; otherwise the bitset row always.
+__device__ __forceinline__ void answer_read(const Index &ix, const uint32_t *M, uint64_t *res, uint64_t *o,
+                                            uint32_t lane, int mode, unsigned long long *counts, uint64_t i) {
+    if (masks_some_rep_empty(ix, M, lane)) {
+        if (counts) {
+            if (lane == 0) counts[i] = 0;
+        } else {
+            write_zeros(o, ix.W, lane);
+        }
+        return;
+    }
+    const uint64_t pc = resolve(ix, M, res, o, lane, mode);
+    if (counts && lane == 0) counts[i] = pc;
 }
 
 }  // namespace rambo

@@ -49,6 +49,11 @@ struct rambo_s {
     int device = 0, n_cu = 0;
     uint64_t rows_bytes = 0;
     bool opaque = false;  // documents are sets of opaque 64-bit terms
+    // id-list queries: per-read answer sizes and scan scratch (grown as
+    // needed; one id-list query at a time per handle)
+    unsigned long long *d_ids_counts = nullptr;
+    uint64_t ids_counts_cap = 0;
+    std::mutex ids_mu;
     uint32_t *rows = nullptr;
     rambo::HashParams *d_hp = nullptr;
     uint4 *d_cells = nullptr;  // [K] phi_r(d) of every repetition, 16 bits each
@@ -92,6 +97,7 @@ struct QueryOpts {
     int early_exit;
     unsigned long long *probes;   // may be null
     int sched;                    // probe schedule (SCHED_*)
+    unsigned long long *counts;   // id-list mode: per-read answer sizes, zero answers not written; or null
 };
 
 // build.hip
@@ -105,18 +111,21 @@ int launch_fold(rambo_s *h, const uint32_t *in, uint32_t *out, uint32_t RWi, uin
 
 // query.hip
 int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *out, hipStream_t s);
-// With hdr (device), the batch is read from it on the device and n is only
-// the capacity the grid is sized for.
 int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *offs, uint64_t n, uint64_t *out,
                           hipStream_t s);
+// With hdr (device), the batch is read from it on the device and n is only
+// the capacity the grid is sized for. With counts, id-list mode (QueryOpts).
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
-                            uint64_t *out, hipStream_t s, int seg, const InputHdr *hdr = nullptr);
+                            uint64_t *out, hipStream_t s, int seg, const InputHdr *hdr = nullptr,
+                            unsigned long long *counts = nullptr);
+// Bitsets to id lists; counts (answer sizes from an id-list mode query, n
+// words) or null to count the bitsets first.
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off,
-               uint64_t ids_cap, hipStream_t s);
+               uint64_t ids_cap, hipStream_t s, const unsigned long long *counts = nullptr);
 
 // batch.hip
 int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                       hipStream_t s);
+                       hipStream_t s, unsigned long long *counts = nullptr);
 void drop_graphs(rambo_s *h);
 
 // Row split: a lane reads SEG words of a row, G = row_words / SEG lanes share

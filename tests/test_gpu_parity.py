@@ -189,13 +189,24 @@ def test_invalid_kmer_values_reported():
         idx.insert(idx.K, np.array([1], dtype=np.uint64))
 
 
-def test_id_lists_match_bitsets():
-    idx, o, dm, reads, want = setup_case("rw32")
+@pytest.mark.parametrize("name", ["rw4", "rw32"])
+def test_id_lists_match_bitsets(name):
+    """Id lists in both forms (answer sizes from the query, bitsets written
+    only for non-empty answers), twice in a row and mixed with bitset
+    queries on the same buffers."""
+    import torch
+    idx, o, dm, reads, want = setup_case(name)
     seqs, offs = reads_to_dev(reads)
-    ids, id_off = idx.query_seqs_ids(seqs, offs, ids_cap=10_000_000)
-    ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
-    for i in range(reads.n):
-        assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(want[i], idx.K))
+    scratch = torch.full((reads.n, idx.W), -1, dtype=torch.int64, device="cuda")
+    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED, rb.MODE_BATCHED):
+        idx.set_mode(mode)
+        ids, id_off = idx.query_seqs_ids(seqs, offs, ids_cap=10_000_000, scratch=scratch)
+        ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
+        for i in range(reads.n):
+            assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(want[i], idx.K)), (mode, i)
+        got = to_host_u64(idx.query_seqs(seqs, offs, out=scratch))
+        assert np.array_equal(got, want)
+    idx.set_mode(rb.MODE_PLAIN)
     with pytest.raises(rb.RamboError) as e:
         idx.query_seqs_ids(seqs, offs, ids_cap=0)
     assert e.value.status == rb.ETRUNC and e.value.required == int(id_off[-1])
