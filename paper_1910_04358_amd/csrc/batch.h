@@ -15,6 +15,8 @@ struct BatchBufs {
     uint32_t *order;           // [4][cap] reads by size class of their first tile
     unsigned long long *cls;   // reads of size class v at cls[16 v]
     unsigned long long *head;  // queue position
+    uint32_t *smask;           // [cap][RW] repetition-0 AND over the scout windows (SCHED_PRESCOUT)
+    uint32_t *live;            // [cap] read not ended by the scout pass (SCHED_PRESCOUT)
     uint64_t cap;
 };
 

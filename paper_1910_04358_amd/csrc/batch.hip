@@ -24,10 +24,6 @@
 
 namespace rambo {
 
-__device__ __forceinline__ uint64_t n_windows(uint64_t beg, uint64_t end) {
-    return end >= beg + 31 ? end - beg - 30 : 0;
-}
-
 // Queue order of the persistent kernel, longest work first so that the last
 // items to start are short. Class c holds the reads whose first tile has
 // [c, c+1) quarters of a tile of windows (class 3 up to a full tile, which
@@ -41,21 +37,29 @@ __global__ void k_batch_reset(BatchBufs bb) {
     if (threadIdx.x < 4) bb.cls[16 * threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t mw, uint32_t tile, BatchBufs bb) {
+// With a scout pass before it (prescout), reads that pass ended are
+// answered already and left out of the queue, and a multi-tile read's
+// running mask starts from its scout AND in repetition 0.
+__global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t mw, uint32_t rw, uint32_t tile,
+                                                    BatchBufs bb, int prescout) {
     const uint64_t n = in->n;
     const uint64_t *__restrict__ offs = in->offs;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63;
-    const bool real = i < n;
+    bool real = i < n;
     uint32_t cls = 0;
-    if (real) {
+    if (real && prescout && !bb.live[i]) {
+        bb.extra[i] = 0;
+        real = false;
+    } else if (real) {
         const uint64_t beg = offs[i], end = offs[i + 1];
         const uint64_t nw = n_windows(beg, end > beg ? end : beg);
         const uint64_t tiles = nw ? (nw + tile - 1) / tile : 1;
         bb.extra[i] = tiles - 1;
         if (tiles > 1) {
             bb.done[i] = 0;
-            for (uint32_t w = 0; w < mw; w++) bb.rmask[i * mw + w] = 0xFFFFFFFFu;
+            for (uint32_t w = 0; w < mw; w++)
+                bb.rmask[i * mw + w] = (prescout && w < rw) ? bb.smask[i * rw + w] : 0xFFFFFFFFu;
         }
         cls = (uint32_t)min<uint64_t>(3, min<uint64_t>(nw, tile) * 4 / tile);
     }
@@ -82,6 +86,93 @@ __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t
         uint64_t slot = bbase[cls] + __popcll(mine & ((1ULL << lane) - 1));
         for (uint32_t k = 0; k < wave; k++) slot += wcount[k][cls];
         bb.order[(uint64_t)cls * bb.cap + slot] = (uint32_t)i;
+    }
+}
+
+// Scout pass of the batched form (SCHED_PRESCOUT), before the queue is
+// built: repetition 0 on every read's scout windows (every 31st window and
+// the last, which together cover every base of the read). A group of GS
+// lanes takes one read, GS / G windows per round (G lanes split a row, as in
+// the main kernel), and ANDs the rounds' rows by lane exchanges. The AND is
+// stored in smask[i], the starting repetition-0 mask of the read's items, and
+// live[i] says whether it is non-empty. With early exit an empty AND ends the
+// read here (Section 3.3.1): its answer (a zero bitset, or a zero answer size
+// in id-list mode) is written now and the read never enters the queue. The
+// grid (up to 8 workgroups per CU, striding over the reads) keeps thousands
+// of reads in flight, which hides the latency of these few dependent steps; a
+// wave of the persistent kernel pays it in full, read by read.
+template <int SEG, int G>
+__global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *in, uint64_t *__restrict__ out,
+                                                     BatchBufs bb, QueryOpts opt) {
+    constexpr int GS = (16 * G < 64) ? 16 * G : 64;  // lanes per read
+    constexpr int SLOTS = GS / G;                   // windows per round
+    const uint8_t *__restrict__ seqs = in->seqs;
+    const uint64_t *__restrict__ offs = in->offs;
+    const uint64_t n = in->n;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t sub = lane % GS, seg = sub % G, slot = sub / G;
+    const uint64_t gmask = (GS >= 64) ? ~0ULL : (((1ULL << GS) - 1) << (lane - sub));  // the group's lanes
+    constexpr uint32_t GPB = 256 / GS;  // reads per workgroup and round of the grid
+    __shared__ unsigned long long blk_issued;
+    if (threadIdx.x == 0) blk_issued = 0;
+    __syncthreads();
+    uint64_t issued = 0;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * GPB; i0 < n; i0 += (uint64_t)gridDim.x * GPB) {
+        const uint64_t i = i0 + threadIdx.x / GS;
+        uint64_t beg = 0, end = 0;
+        if (i < n) {
+            beg = offs[i];
+            end = offs[i + 1];
+            if (end < beg) end = beg;
+        }
+        const uint64_t nw = n_windows(beg, end);
+        const uint64_t ns = nw ? scout_count(0, nw) : 0;
+        Seg<SEG> acc;
+#pragma unroll
+        for (int s = 0; s < SEG; s++) acc.w[s] = 0xFFFFFFFFu;
+        bool live = true;  // uniform over the group
+        for (uint64_t k0 = 0;; k0 += SLOTS) {
+            const bool active = live && k0 < ns;
+            if (__ballot(active) == 0) break;
+            Window wv;
+            wv.canon = 0;
+            wv.valid = false;
+            if (active && k0 + slot < ns) wv = window_at(seqs + beg + scout_pos(0, nw, k0 + slot));
+            Seg<SEG> cm[1];
+#pragma unroll
+            for (int s = 0; s < SEG; s++) cm[0].w[s] = 0xFFFFFFFFu;
+            if (wv.valid) probe_reps<SEG, 0, 1>(ix, ix.hp->h, wv.canon, seg, cm);
+            issued += (uint64_t)__popcll(__ballot(wv.valid && seg == 0));
+            uint32_t o = 0;
+#pragma unroll
+            for (int s = 0; s < SEG; s++) {
+                uint32_t v = cm[0].w[s];
+#pragma unroll
+                for (int d = G; d < GS; d <<= 1) v &= (uint32_t)__shfl_xor((int)v, d);
+                acc.w[s] &= v;
+                o |= acc.w[s];
+            }
+            if (opt.early_exit && (__ballot(o != 0) & gmask) == 0) live = false;
+        }
+        if (i < n) {
+            if (slot == 0)
+#pragma unroll
+                for (int s = 0; s < SEG; s++) bb.smask[i * ix.RW + seg * SEG + s] = acc.w[s];
+            if (sub == 0) bb.live[i] = live ? 1u : 0u;
+            if (!live) {
+                if (opt.counts) {
+                    if (sub == 0) opt.counts[i] = 0;
+                } else {
+                    for (uint32_t w = sub; w < ix.W; w += GS) out[i * ix.W + w] = 0;
+                }
+            }
+        }
+    }
+    // one counter update per workgroup (same-address atomics serialise)
+    if (opt.probes) {
+        if (lane == 0 && issued) atomicAdd(&blk_issued, (unsigned long long)issued);
+        __syncthreads();
+        if (threadIdx.x == 0 && blk_issued) atomicAdd(opt.probes, blk_issued * ix.eta);
     }
 }
 
@@ -139,8 +230,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
 
     const uint64_t n = in->n;
     const uint64_t n_extra = bb.extra_off[n];
-    const uint64_t total = n + n_extra;
     const uint64_t c3 = uniform64(bb.cls[48]), c2 = uniform64(bb.cls[32]), c1 = uniform64(bb.cls[16]);
+    const uint64_t total = c3 + c2 + c1 + uniform64(bb.cls[0]) + n_extra;  // queued reads and extra tiles
     uint64_t issued = 0;
     for (;;) {
         uint64_t t0 = 0;
@@ -175,6 +266,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
             // another tile of the read may have emptied its masks already
             const bool skip = ntiles > 1 && opt.early_exit && read_dead(ix, rm, lane);
             init_masks(ix, M, lane);
+            if (opt.sched == SCHED_PRESCOUT && ntiles == 1)
+                for (uint32_t w = lane; w < ix.RW; w += 64) M[w] = bb.smask[i * ix.RW + w];
             if (!skip) {
                 const uint64_t w_hi = min(nwin, (c + 1) * (uint64_t)tile);
                 issued += probe_windows<SEG, G>(ix, seqs, beg, end, c * (uint64_t)tile, w_hi, lane, M,
@@ -224,12 +317,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
 
 static constexpr uint32_t kMaxLds = 64 * 1024;
 
-static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, hipStream_t s) {
+static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *out, unsigned long long *counts,
+                        hipStream_t s) {
     const uint32_t mw = h->R * h->RW;
+    const bool pre = tu.sched == SCHED_PRESCOUT;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bg.bb);
     HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, bg.in, mw,
-                       (uint32_t)tu.tile, bg.bb);
+    if (pre) {
+        const Index ix = make_index(h);
+        const int G = (int)h->RW / tu.seg;
+        // a grid of at most 8 workgroups per CU strides over the reads
+        const uint64_t GS = std::min(64, 16 * G);
+        const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((bg.cap * GS + 255) / 256, 8ull * h->n_cu));
+        QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched, counts};
+#define RAMBO_SPLIT_BODY_                                                                                   \
+    hipLaunchKernelGGL((k_batch_scout<SEG, G>), dim3((unsigned)blocks), dim3(256), 0, s, ix, bg.in, out, bg.bb, opt)
+        RAMBO_DISPATCH_SPLIT(tu.seg, G)
+#undef RAMBO_SPLIT_BODY_
+        HIP_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, bg.in, mw, h->RW,
+                       (uint32_t)tu.tile, bg.bb, pre ? 1 : 0);
     HIP_CHECK(hipGetLastError());
     // the header's first field is n
     return launch_exclusive_scan(bg.bb.extra, &bg.in->n, bg.cap, bg.bb.extra_off, bg.parts, s);
@@ -294,8 +402,10 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
                              const InputHdr *init) {
     const size_t mw = (size_t)h->R * h->RW;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t b_mask = 0, b_done = 0, b_extra = 0, b_off = 0, b_parts = 0, b_order = 0;
+    size_t b_mask = 0, b_done = 0, b_extra = 0, b_off = 0, b_parts = 0, b_order = 0, b_smask = 0, b_live = 0;
     if (batch_bufs) {
+        b_smask = al(cap * h->RW * 4);
+        b_live = al(cap * 4);
         b_mask = al(cap * mw * 4);
         b_done = al(cap * 4);
         b_extra = al(cap * 8);
@@ -303,8 +413,10 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
         b_parts = al(scan_parts_needed(cap) * 8);
         b_order = al(4 * cap * 4);
     }
-    HIP_CHECK(hipMalloc(&bg.mem, b_mask + b_done + b_extra + b_off + b_parts + b_order + 640 + 256));
+    HIP_CHECK(hipMalloc(&bg.mem, b_mask + b_done + b_extra + b_off + b_parts + b_order + b_smask + b_live + 640 + 256));
     char *p = (char *)bg.mem;
+    bg.bb.smask = b_smask ? (uint32_t *)p : nullptr; p += b_smask;
+    bg.bb.live = b_live ? (uint32_t *)p : nullptr; p += b_live;
     bg.parts = (uint64_t *)p; p += b_parts;
     bg.bb.rmask = (uint32_t *)p; p += b_mask;
     bg.bb.done = (uint32_t *)p; p += b_done;
@@ -337,7 +449,8 @@ int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const I
     bg->tune = tu;
     int st = alloc_graph_state(h, *bg, cap, true, in_dev, init);
     if (st == RAMBO_OK)
-        st = capture(h, &bg->graph_prep, &bg->exec_prep, [&](hipStream_t s) { return enqueue_prep(h, tu, *bg, s); });
+        st = capture(h, &bg->graph_prep, &bg->exec_prep,
+                     [&](hipStream_t s) { return enqueue_prep(h, tu, *bg, out, counts, s); });
     if (st == RAMBO_OK)
         st = capture(h, &bg->graph_main, &bg->exec_main,
                      [&](hipStream_t s) { return enqueue_main(h, tu, *bg, out, s, counts); });
@@ -412,7 +525,7 @@ bool tune_valid(const rambo_s *h, const Tune &t) {
     return (t.seg == 1 || t.seg == 2 || t.seg == 4) && (int)h->RW % t.seg == 0 &&
            split_supported(t.seg, (int)h->RW / t.seg) && t.tile >= 64 && t.tile % 64 == 0 && t.tile <= (1 << 20) &&
            t.waves_per_cu >= 1 && t.waves_per_cu <= 64 && (t.wpb == 1 || t.wpb == 2 || t.wpb == 4) && t.grab >= 1 &&
-           t.grab <= 64 && t.sched >= 0 && t.sched <= 2;
+           t.grab <= 64 && t.sched >= 0 && t.sched <= 3;
 }
 
 static std::string tune_key(const rambo_s *h) {
@@ -522,7 +635,7 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
             if (t.grab != best.grab && (st = consider(t))) return st;
         }
         for (int wpb : {1, 2, 4}) { Tune t = best; t.wpb = wpb; if (t.wpb != best.wpb && (st = consider(t))) return st; }
-        for (int sched : {0, 1, 2}) {
+        for (int sched : {0, 1, 2, 3}) {
             Tune t = best; t.sched = sched;
             if (sched != best.sched && (st = consider(t))) return st;
         }

@@ -299,7 +299,10 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     const Index ix = make_index(h);
     const int G = (int)h->RW / seg;
     const int WPB = 4;
-    const bool stage = h->tune.sched == SCHED_SCOUT;
+    // (the plain form scouts inside its kernel: a separate scout pass is a
+    // step of the batched form's queue)
+    const int sched = h->tune.sched == SCHED_PRESCOUT ? SCHED_SCOUT : h->tune.sched;
+    const bool stage = sched == SCHED_SCOUT;
     int use_res = 1;
     size_t lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, true, stage).total * 4;
     if (lds > kMaxLds) {
@@ -308,7 +311,7 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     }
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, h->tune.sched, counts};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, sched, counts};
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
                        n, hdr, out, opt, use_res)

@@ -451,7 +451,14 @@ enum : int {
     SCHED_STEP = 0,   // per step of 64 windows: repetition 0, then the others
     SCHED_SWEEP = 1,  // repetition 0 over every step of the span, then the others
     SCHED_SCOUT = 2,  // as SWEEP, after repetition 0 on every 31st window
+    SCHED_PRESCOUT = 3,  // batched form: the scout windows of every read in a
+                         // pass of their own before the work queue is built
 };
+
+// windows of 31 bases in the bytes [beg, end)
+__device__ __forceinline__ uint64_t n_windows(uint64_t beg, uint64_t end) {
+    return end >= beg + 31 ? end - beg - 30 : 0;
+}
 
 // Scout windows of a span [w_lo, w_hi): w_lo, w_lo + 31, ... and the last
 // window. Windows 31 apart cover every base of the span, so a read holding
@@ -465,7 +472,8 @@ __device__ __forceinline__ uint64_t scout_pos(uint64_t w_lo, uint64_t w_hi, uint
     return min(w_lo + 31 * i, w_hi - 1);
 }
 __device__ __forceinline__ bool is_scout(uint64_t w_lo, uint64_t w_hi, uint64_t w) {
-    return (w - w_lo) % 31 == 0 || w == w_hi - 1;
+    // (offsets within one read fit 32 bits)
+    return (uint32_t)(w - w_lo) % 31u == 0 || w == w_hi - 1;
 }
 
 // Bytes [lo, hi) of seqs (inside one read) to the wave's LDS staging area,
@@ -535,6 +543,11 @@ __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t
                                                   uint32_t *M, bool early_exit, int sched, uint8_t *stage) {
     uint64_t issued = 0;
     const bool scout = sched == SCHED_SCOUT && stage != nullptr && w_lo < w_hi;
+    // Repetition 0 skips the scout windows: those of this span after the
+    // scout pass above, or (SCHED_PRESCOUT) those of the whole read, which a
+    // pass of their own has probed and ANDed into the masks already.
+    const bool skip0 = scout || sched == SCHED_PRESCOUT;
+    const uint64_t sk_lo = scout ? w_lo : 0, sk_hi = scout ? w_hi : n_windows(beg, end);
     if (scout) {
         const uint64_t ns = scout_count(w_lo, w_hi);
         for (uint64_t i0 = 0; i0 < ns; i0 += 64) {
@@ -559,14 +572,14 @@ __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t
             if (early_exit && !alive) return issued;
         }
     }
-    if ((sched == SCHED_SWEEP || scout) && ix.R > 1) {
+    if ((sched == SCHED_SWEEP || skip0) && ix.R > 1) {
         {
             StepBytes next = load_bytes(seqs, beg, end, w_lo, lane);
             for (uint64_t w = w_lo; w < w_hi; w += 64) {
                 const StepBytes cur = next;
                 if (w + 64 < w_hi) next = load_bytes(seqs, beg, end, w + 64, lane);
                 const Window wv = extract_windows(cur.c0, cur.c1, lane);
-                const bool valid = wv.valid && (w + lane < w_hi) && !(scout && is_scout(w_lo, w_hi, w + lane));
+                const bool valid = wv.valid && (w + lane < w_hi) && !(skip0 && is_scout(sk_lo, sk_hi, w + lane));
                 const bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid, lane, M);
                 issued += (uint64_t)__popcll(__ballot(valid));
                 if (early_exit && !alive) return issued;
@@ -596,7 +609,7 @@ __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t
         const Window wv = extract_windows(cur.c0, cur.c1, lane);
         const bool valid = wv.valid && (w + lane < w_hi);
         // (with one repetition a scout pass has probed its windows already)
-        const bool valid0 = valid && !(scout && is_scout(w_lo, w_hi, w + lane));
+        const bool valid0 = valid && !(skip0 && is_scout(sk_lo, sk_hi, w + lane));
         bool alive = probe_group<SEG, G, 0, 1>(ix, step_params(ix), wv, valid0, lane, M);
         issued += (uint64_t)__popcll(__ballot(valid0));
         const uint64_t nv = (uint64_t)__popcll(__ballot(valid));

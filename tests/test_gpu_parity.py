@@ -110,7 +110,7 @@ def test_read_queries_every_form_bit_exact(name):
             idx.set_resolve(resolve)
             for ee in (True, False):
                 idx.set_early_exit(ee)
-                for sched in (0, 1, 2):
+                for sched in (0, 1, 2, 3):
                     t = idx.get_tune()
                     t.sched = sched
                     idx.set_tune(t)
@@ -132,7 +132,7 @@ def test_batched_launch_shapes_agree(name):
     for seg in segs:
         for tile, wpc, wpb, grab, sched in ((64, 4, 1, 1, 0), (128, 8, 4, 2, 1), (512, 32, 2, 4, 1),
                                             (256, 16, 2, 1, 0), (1024, 16, 4, 1, 1), (64, 8, 4, 1, 2),
-                                            (1024, 16, 2, 2, 2)):
+                                            (1024, 16, 2, 2, 2), (64, 8, 1, 1, 3), (256, 16, 4, 2, 3)):
             idx.set_tune(rb.Tune(seg, tile, wpc, wpb, grab, sched))
             got = to_host_u64(idx.query_seqs(seqs, offs))
             assert np.array_equal(got, want), (seg, tile, wpc, wpb, grab, sched)
@@ -198,12 +198,15 @@ def test_id_lists_match_bitsets(name):
     idx, o, dm, reads, want = setup_case(name)
     seqs, offs = reads_to_dev(reads)
     scratch = torch.full((reads.n, idx.W), -1, dtype=torch.int64, device="cuda")
-    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED, rb.MODE_BATCHED):
+    for mode, sched in ((rb.MODE_PLAIN, 2), (rb.MODE_BATCHED, 2), (rb.MODE_BATCHED, 3), (rb.MODE_BATCHED, 3)):
         idx.set_mode(mode)
+        t = idx.get_tune()
+        t.sched = sched
+        idx.set_tune(t)
         ids, id_off = idx.query_seqs_ids(seqs, offs, ids_cap=10_000_000, scratch=scratch)
         ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
         for i in range(reads.n):
-            assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(want[i], idx.K)), (mode, i)
+            assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(want[i], idx.K)), (mode, sched, i)
         got = to_host_u64(idx.query_seqs(seqs, offs, out=scratch))
         assert np.array_equal(got, want)
     idx.set_mode(rb.MODE_PLAIN)
@@ -291,7 +294,7 @@ def test_probe_counter_closed_form_without_early_exit(name):
         idx.set_mode(mode)
         for ee in (False, True):
             idx.set_early_exit(ee)
-            for sched in (0, 1, 2):
+            for sched in (0, 1, 2, 3):
                 t = idx.get_tune()
                 t.sched = sched
                 idx.set_tune(t)
