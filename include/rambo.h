@@ -264,11 +264,11 @@ typedef struct {
                          form: 0 = per step of 64 windows, repetition 0 then
                          the others; 1 = repetition 0 over the whole work
                          item first, then the others; 2 = as 1, after
-                         repetition 0 on every 31st window of the item;
-                         3 = batched form: that scout step over every read
-                         of the batch in a pass of its own before the work
-                         queue, which then holds only the reads it did not
-                         end (the plain form takes 3 as 2) */
+                         repetition 0 on every 31st window (and the last)
+                         first: the plain form does it in its kernel, read
+                         by read; the batched form in a pass of its own over
+                         every read of the batch before the work queue, which
+                         then holds only the reads that pass did not end */
     int tuned;        /* output of rambo_get_tune: 1 once chosen or set */
 } rambo_tune_t;
 

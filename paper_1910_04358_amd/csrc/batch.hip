@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t
     }
 }
 
-// Scout pass of the batched form (SCHED_PRESCOUT), before the queue is
+// Scout pass of the batched form (SCHED_SCOUT), before the queue is
 // built: repetition 0 on every read's scout windows (every 31st window and
 // the last, which together cover every base of the read). A group of GS
 // lanes takes one read, GS / G windows per round (G lanes split a row, as in
@@ -223,10 +223,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
     extern __shared__ __align__(16) uint64_t smem64[];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t mw = ix.R * ix.RW;
-    const WaveLds L = wave_lds(mw, ix.W, use_res != 0, opt.sched == SCHED_SCOUT);
+    // (no staging area: this form scouts in a pass of its own)
+    const WaveLds L = wave_lds(mw, ix.W, use_res != 0, false);
     uint32_t *M = reinterpret_cast<uint32_t *>(smem64) + wave * L.total;
     uint64_t *res = use_res ? reinterpret_cast<uint64_t *>(M + L.res) : nullptr;
-    uint8_t *stage = opt.sched == SCHED_SCOUT ? reinterpret_cast<uint8_t *>(M + L.stage) : nullptr;
+    uint8_t *stage = nullptr;
 
     const uint64_t n = in->n;
     const uint64_t n_extra = bb.extra_off[n];
@@ -320,7 +321,7 @@ static constexpr uint32_t kMaxLds = 64 * 1024;
 static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *out, unsigned long long *counts,
                         hipStream_t s) {
     const uint32_t mw = h->R * h->RW;
-    const bool pre = tu.sched == SCHED_PRESCOUT;
+    const bool pre = tu.sched == SCHED_SCOUT;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bg.bb);
     HIP_CHECK(hipGetLastError());
     if (pre) {
@@ -348,14 +349,15 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
     const int G = (int)h->RW / tu.seg;
-    const bool stage = tu.sched == SCHED_SCOUT;
     int use_res = 1;
-    size_t lds = (size_t)tu.wpb * wave_lds(mw, h->W, true, stage).total * 4;
+    size_t lds = (size_t)tu.wpb * wave_lds(mw, h->W, true, false).total * 4;
     if (lds > kMaxLds) {
         use_res = 0;
-        lds = (size_t)tu.wpb * wave_lds(mw, h->W, false, stage).total * 4;
+        lds = (size_t)tu.wpb * wave_lds(mw, h->W, false, false).total * 4;
     }
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched, counts};
+    // the scout schedule has run its scout windows in the scout pass already
+    const int ksched = tu.sched == SCHED_SCOUT ? SCHED_PRESCOUT : tu.sched;
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, ksched, counts};
     // a persistent grid must be resident: never more workgroups than fit
 #define RAMBO_SPLIT_BODY_                                                                                  \
     {                                                                                                      \
@@ -525,7 +527,7 @@ bool tune_valid(const rambo_s *h, const Tune &t) {
     return (t.seg == 1 || t.seg == 2 || t.seg == 4) && (int)h->RW % t.seg == 0 &&
            split_supported(t.seg, (int)h->RW / t.seg) && t.tile >= 64 && t.tile % 64 == 0 && t.tile <= (1 << 20) &&
            t.waves_per_cu >= 1 && t.waves_per_cu <= 64 && (t.wpb == 1 || t.wpb == 2 || t.wpb == 4) && t.grab >= 1 &&
-           t.grab <= 64 && t.sched >= 0 && t.sched <= 3;
+           t.grab <= 64 && t.sched >= 0 && t.sched <= 2;
 }
 
 static std::string tune_key(const rambo_s *h) {
@@ -635,7 +637,7 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
             if (t.grab != best.grab && (st = consider(t))) return st;
         }
         for (int wpb : {1, 2, 4}) { Tune t = best; t.wpb = wpb; if (t.wpb != best.wpb && (st = consider(t))) return st; }
-        for (int sched : {0, 1, 2, 3}) {
+        for (int sched : {0, 1, 2}) {
             Tune t = best; t.sched = sched;
             if (sched != best.sched && (st = consider(t))) return st;
         }

@@ -299,9 +299,7 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     const Index ix = make_index(h);
     const int G = (int)h->RW / seg;
     const int WPB = 4;
-    // (the plain form scouts inside its kernel: a separate scout pass is a
-    // step of the batched form's queue)
-    const int sched = h->tune.sched == SCHED_PRESCOUT ? SCHED_SCOUT : h->tune.sched;
+    const int sched = h->tune.sched;  // (this form scouts inside its kernel)
     const bool stage = sched == SCHED_SCOUT;
     int use_res = 1;
     size_t lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, true, stage).total * 4;

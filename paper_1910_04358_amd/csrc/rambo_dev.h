@@ -451,8 +451,9 @@ enum : int {
     SCHED_STEP = 0,   // per step of 64 windows: repetition 0, then the others
     SCHED_SWEEP = 1,  // repetition 0 over every step of the span, then the others
     SCHED_SCOUT = 2,  // as SWEEP, after repetition 0 on every 31st window
-    SCHED_PRESCOUT = 3,  // batched form: the scout windows of every read in a
-                         // pass of their own before the work queue is built
+    // (internal) the batched form's SCHED_SCOUT: a pass of its own has probed
+    // the scout windows of every read before the work queue was built
+    SCHED_PRESCOUT = 3,
 };
 
 // windows of 31 bases in the bytes [beg, end)

@@ -36,7 +36,7 @@ struct Tune {
     int waves_per_cu = 16; // resident waves per CU of the persistent grid
     int wpb = 4;          // waves per workgroup
     int grab = 1;         // work items taken per queue access
-    int sched = 3;        // probe schedule of a read's windows (SCHED_*; 3 = scout pass, batched form)
+    int sched = 2;        // probe schedule of a read's windows (SCHED_*; 2 = scout)
 };
 
 struct BatchGraph;  // batched-form state for one set of buffers (batch.hip)
