@@ -287,6 +287,7 @@ def main():
     ap.add_argument("--no-kmers", action="store_true", help="skip the single k-mer query workload")
     ap.add_argument("--no-terms", action="store_true", help="skip the word-term (web document) workloads")
     ap.add_argument("--no-k101000", action="store_true", help="skip the K=101,000 (96 GiB) workload")
+    ap.add_argument("--no-full", action="store_true", help="skip the runs without early exit")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a 1 GiB device copy (scale for hardware byte counters)")
     ap.add_argument("--only", choices=["plain", "batched"], default=None,
@@ -373,6 +374,32 @@ def main():
     achieved = alg_bytes / (batched_ms * 1e-3) / 1e9
     value = n_kmers / batched_ms * 1e3
 
+    # Without early exit every valid window is probed in every repetition
+    # (k-mers x R x eta probes): the same batch, both forms, so that the
+    # roofline fraction is also shown on work that nothing skips.
+    full = None
+    if args.only is None and not args.no_full:
+        full = {}
+        idx.set_early_exit(False)
+        for name, mode in (("plain", MODE_PLAIN), ("batched", MODE_BATCHED)):
+            idx.set_mode(mode)
+            ms = time_steps(step, min(args.steps, 5), 1)
+            if not torch.equal(out, ref):
+                raise SystemExit("results without early exit differ")
+            idx.set_probe_counter(probes)
+            probes.zero_()
+            step()
+            torch.cuda.synchronize()
+            n_pr = int(probes.item())
+            idx.set_probe_counter(None)
+            by = n_pr * max(GRANULE, row_bytes) + io_bytes
+            full[name] = {"ms_per_step": ms, "kmer_per_s": n_kmers / ms * 1e3, "probes": n_pr,
+                          "achieved_GBps": by / ms / 1e6, "frac": by / ms / 1e6 / HBM_PEAK_GBS}
+            log("no early exit, %s: %.3f ms/step, %d probes, %.0f GB/s (%.2f of peak)"
+                % (name, ms, n_pr, by / ms / 1e6, by / ms / 1e6 / HBM_PEAK_GBS))
+        idx.set_early_exit(True)
+        idx.set_mode(MODE_BATCHED)
+
     # the empirical ceiling of the probe pattern: uniformly random row reads
     # over the index's own buffer (random-access microbenchmark)
     ceiling = None
@@ -452,6 +479,7 @@ def main():
                      "frac_of_ceiling": (issued / (batched_ms * 1e-3) / ceiling["probes_per_s"]) if ceiling else None},
         "cpu_baseline": cpu,
         "served": served,
+        "no_early_exit": full,
         "kmer_queries": kq,
         "web_terms": web,
     }
