@@ -154,7 +154,7 @@ def k101000_run(dev, steps, warmup):
     torch.cuda.synchronize()
     issued = int(probes.item())
     idx.set_probe_counter(None)
-    ids_ms = time_steps(lambda: idx.query_seqs_ids(seqs, offs, ids_cap=50_000_000, scratch=out), 3, 1)
+    ids_ms = time_steps(lambda: idx.query_seqs_ids(seqs, offs, ids_cap=50_000_000, scratch=out, check=False), 3, 1)
     rec = {"workload": w.name, "index_bytes": idx.index_bytes, "build_ms": build_ms,
            "build_input_GBps_u64_kmers": build_kmers * 8 / build_ms / 1e6, "reads": reads.n, "kmers": n_kmers,
            "plain_ms": plain_ms, "batched_ms": ms, "kmer_per_s": n_kmers / ms * 1e3, "reads_per_s": reads.n / ms * 1e3,

@@ -67,6 +67,7 @@ static void free_device(rambo_s *h) {
     if (h->d_hp) (void)hipFree(h->d_hp);
     if (h->d_cells) (void)hipFree(h->d_cells);
     if (h->d_ids_counts) (void)hipFree(h->d_ids_counts);
+    if (h->d_ids_aux) (void)hipFree(h->d_ids_aux);
     if (h->d_boff) (void)hipFree(h->d_boff);
     if (h->d_bdoc) (void)hipFree(h->d_bdoc);
     if (h->d_invalid) (void)hipFree(h->d_invalid);
@@ -374,15 +375,18 @@ RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64
     if (!id_offsets) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null id_offsets");
     if (h->opaque) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: the index holds opaque terms, not 31-mers");
     if (n > 0 && (!scratch || !seqs || !offsets)) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null array");
-    if (n == 0) return launch_ids(h, scratch, 0, ids, id_offsets, ids_cap, (hipStream_t)stream);
+    if (n == 0) return launch_ids(h, scratch, 0, ids, id_offsets, ids_cap, (hipStream_t)stream, nullptr, nullptr);
     // id-list mode: the query writes each read's answer size and the bitsets
     // of non-empty answers only
     std::lock_guard<std::mutex> g(h->ids_mu);
     if (h->ids_counts_cap < n) {
         if (h->d_ids_counts) (void)hipFree(h->d_ids_counts);
+        if (h->d_ids_aux) (void)hipFree(h->d_ids_aux);
         h->d_ids_counts = nullptr;
+        h->d_ids_aux = nullptr;
         h->ids_counts_cap = 0;
         HIP_CHECK(hipMalloc(&h->d_ids_counts, n * 8));
+        HIP_CHECK(hipMalloc(&h->d_ids_aux, ids_aux_words(n) * 8));
         h->ids_counts_cap = n;
     }
     const hipStream_t s = (hipStream_t)stream;
@@ -391,7 +395,7 @@ RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64
                  : launch_query_seqs_plain(h, seqs, offsets, n, scratch, s, default_seg(h->RW), nullptr,
                                            h->d_ids_counts);
     if (st != RAMBO_OK) return st;
-    return launch_ids(h, scratch, n, ids, id_offsets, ids_cap, s, h->d_ids_counts);
+    return launch_ids(h, scratch, n, ids, id_offsets, ids_cap, s, h->d_ids_counts, h->d_ids_aux);
 }
 
 RAMBO_API int rambo_set_mode(rambo_t *h, int mode) {

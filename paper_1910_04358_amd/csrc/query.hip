@@ -345,47 +345,49 @@ int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *off
 // -------------------------------------------------------------------------
 // bitsets -> ascending id lists
 // -------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_count_bits(const uint64_t *__restrict__ bits, uint64_t n, uint32_t W,
-                                                    uint64_t *__restrict__ counts) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (i >= n) return;
-    uint64_t c = 0;
-    for (uint32_t w = lane; w < W; w += 64) c += __popcll(bits[i * W + w]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-    if (lane == 0) counts[i] = c;
-}
-
+// One wave per 64 reads: the reads with ids (a few per cent in id-list
+// workloads) are found with one ballot and compacted one after the other by
+// the whole wave; empty answers cost nothing more.
 __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ bits, uint64_t n, uint32_t W,
                                                  const uint64_t *__restrict__ off, uint32_t *__restrict__ ids) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (i >= n) return;
-    uint64_t base = off[i];
-    if (off[i + 1] == base) return;  // no id: the bitset need not be read again
-    for (uint32_t w0 = 0; w0 < W; w0 += 64) {
-        const uint32_t w = w0 + lane;
-        uint64_t word = w < W ? bits[i * W + w] : 0;
-        const uint32_t pc = __popcll(word);
-        uint32_t incl = pc;
+    const uint64_t i0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
+    if (i0 >= n) return;
+    const uint64_t mine = i0 + lane;
+    uint64_t todo = __ballot(mine < n && off[mine + 1] != off[mine]);
+    while (todo) {
+        const uint64_t i = i0 + (uint64_t)__builtin_ctzll(todo);
+        todo &= todo - 1;
+        uint64_t base = off[i];
+        for (uint32_t w0 = 0; w0 < W; w0 += 64) {
+            const uint32_t w = w0 + lane;
+            uint64_t word = w < W ? bits[i * W + w] : 0;
+            const uint32_t pc = __popcll(word);
+            uint32_t incl = pc;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t v = __shfl_up(incl, d);
-            if ((int)lane >= d) incl += v;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t v = __shfl_up(incl, d);
+                if ((int)lane >= d) incl += v;
+            }
+            uint64_t pos = base + incl - pc;
+            while (word) {
+                const uint32_t b = (uint32_t)__builtin_ctzll(word);
+                word &= word - 1;
+                ids[pos++] = w * 64 + b;
+            }
+            base += __shfl(incl, 63);
         }
-        uint64_t pos = base + incl - pc;
-        while (word) {
-            const uint32_t b = (uint32_t)__builtin_ctzll(word);
-            word &= word - 1;
-            ids[pos++] = w * 64 + b;
-        }
-        base += __shfl(incl, 63);
     }
 }
 
+__global__ void k_store_u64(uint64_t *p, uint64_t v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
+uint64_t ids_aux_words(uint64_t n) { return scan_parts_needed(n) + 1; }
+
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off, uint64_t ids_cap,
-               hipStream_t s, const unsigned long long *given) {
+               hipStream_t s, const unsigned long long *counts, uint64_t *aux) {
     const uint32_t W = (uint32_t)h->W;
     uint64_t total = 0;
     if (n == 0) {
@@ -393,39 +395,23 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
         HIP_CHECK(hipStreamSynchronize(s));
         return RAMBO_OK;
     }
-    uint64_t *counts = nullptr;
-    const uint64_t nparts = scan_parts_needed(n);
-    HIP_CHECK(hipMallocAsync((void **)&counts, (n + nparts + 1) * 8, s));
-    uint64_t *parts = counts + n, *d_n = parts + nparts;
-    const uint64_t n_host = n;
-    HIP_CHECK(hipMemcpyAsync(d_n, &n_host, 8, hipMemcpyHostToDevice, s));
-    const unsigned blocks = (unsigned)((n + 3) / 4);
-    if (given) HIP_CHECK(hipMemcpyAsync(counts, given, n * 8, hipMemcpyDeviceToDevice, s));
-    else hipLaunchKernelGGL(k_count_bits, dim3(blocks), dim3(256), 0, s, bits, n, W, counts);
-    int sst = launch_exclusive_scan(counts, d_n, n, id_off, parts, s);
-    if (sst != RAMBO_OK) {
-        (void)hipFreeAsync(counts, s);
-        return sst;
-    }
+    uint64_t *parts = aux, *d_n = aux + scan_parts_needed(n);
+    hipLaunchKernelGGL(k_store_u64, dim3(1), dim3(64), 0, s, d_n, n);
+    HIP_CHECK(hipGetLastError());
+    int sst = launch_exclusive_scan(reinterpret_cast<const uint64_t *>(counts), d_n, n, id_off, parts, s);
+    if (sst != RAMBO_OK) return sst;
     hipError_t e = hipMemcpyAsync(&total, id_off + n, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(counts, s);
-        return fail(RAMBO_EDEVICE, "rambo_query_seqs_ids: %s", hipGetErrorString(e));
-    }
-    if (total > ids_cap) {
-        (void)hipFreeAsync(counts, s);
+    if (e != hipSuccess) return fail(RAMBO_EDEVICE, "rambo_query_seqs_ids: %s", hipGetErrorString(e));
+    if (total > ids_cap)
         return fail(RAMBO_ETRUNC, "rambo_query_seqs_ids: %llu ids do not fit %llu", (unsigned long long)total,
                     (unsigned long long)ids_cap);
-    }
     if (total > 0) {
-        if (!ids) {
-            (void)hipFreeAsync(counts, s);
-            return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null ids");
-        }
-        hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, bits, n, W, id_off, ids);
+        if (!ids) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null ids");
+        const uint64_t waves = (n + 63) / 64;
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, bits, n, W, id_off, ids);
+        HIP_CHECK(hipGetLastError());
     }
-    HIP_CHECK(hipFreeAsync(counts, s));
     HIP_CHECK(hipStreamSynchronize(s));
     return RAMBO_OK;
 }

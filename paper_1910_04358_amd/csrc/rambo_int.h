@@ -52,6 +52,7 @@ struct rambo_s {
     // id-list queries: per-read answer sizes and scan scratch (grown as
     // needed; one id-list query at a time per handle)
     unsigned long long *d_ids_counts = nullptr;
+    uint64_t *d_ids_aux = nullptr;
     uint64_t ids_counts_cap = 0;
     std::mutex ids_mu;
     uint32_t *rows = nullptr;
@@ -118,10 +119,11 @@ int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *off
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
                             uint64_t *out, hipStream_t s, int seg, const InputHdr *hdr = nullptr,
                             unsigned long long *counts = nullptr);
-// Bitsets to id lists; counts (answer sizes from an id-list mode query, n
-// words) or null to count the bitsets first.
+// Bitsets of an id-list mode query to id lists: counts holds the n answer
+// sizes the query wrote, aux ids_aux_words(n) words of scan scratch.
+uint64_t ids_aux_words(uint64_t n);
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off,
-               uint64_t ids_cap, hipStream_t s, const unsigned long long *counts = nullptr);
+               uint64_t ids_cap, hipStream_t s, const unsigned long long *counts, uint64_t *aux);
 
 // batch.hip
 int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
