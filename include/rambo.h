@@ -58,6 +58,8 @@ enum {
     RAMBO_EDEVICE = -3, /* HIP runtime error */
     RAMBO_ETRUNC = -4,  /* id output too small (see rambo_query_seqs_ids) */
     RAMBO_EBUSY = -5,   /* server queue full / admission refused */
+    RAMBO_EIO = -6,     /* index file: open, read or write failed, or not a
+                           valid index file (see rambo_save) */
 };
 
 /* Query execution forms for rambo_query_seqs. */
@@ -134,6 +136,7 @@ typedef struct {
     uint64_t W;          /* result words per query */
     uint64_t index_bytes;/* R * m * row_words * 4 */
     void *rows;          /* device pointer to rows[R][m][row_words] (uint32) */
+    uint32_t flags;      /* creation flags (RAMBO_TERMS_OPAQUE) */
 } rambo_layout_t;
 
 int rambo_layout(const rambo_t *h, rambo_layout_t *out);
@@ -156,6 +159,28 @@ int rambo_dump_bfu(rambo_t *h, uint32_t r, uint32_t b, uint64_t *out);
 /* Copy `bytes` bytes of the raw row array, starting at byte `offset`, to the
  * host buffer `dst`. Synchronous. */
 int rambo_copy_rows(rambo_t *h, uint64_t offset, uint64_t bytes, void *dst);
+
+/* Index files: the index is built once and queried many times (Section 5.3
+ * builds shards on many nodes and queries the stored indexes). rambo_save
+ * writes a 96-byte little-endian header -- magic "RAMBOIX1", format version
+ * 1, header size, K, m, seed, row array bytes, checksum, B, R, eta, flags,
+ * row_words -- and then the raw row array (rows[R][m][row_words], uint32), so
+ * the file is rambo_index_bytes + 96 bytes. The hash functions are not
+ * stored: they are derived from (seed, B, R, eta, m) as at creation (a folded
+ * index is stored with its folded B, which derives the folded partition).
+ * The checksum covers the row array (computed on the device) and the
+ * header's parameters; rambo_load recomputes it after the upload. Rows stream through two pinned host
+ * buffers of 64 MiB, copies overlapping file I/O. Both are synchronous and
+ * must not overlap an insert on the same handle.
+ * rambo_save: RAMBO_EINVAL on a null argument, RAMBO_EIO if the file cannot
+ * be written (a partial file may remain), RAMBO_EDEVICE/ENOMEM on runtime
+ * errors.
+ * rambo_load: a new handle on the current device, or NULL with
+ * rambo_last_status() = RAMBO_EIO for a missing, short, foreign or corrupted
+ * file (bad magic, version, sizes or checksum), RAMBO_EINVAL for parameters
+ * out of range, RAMBO_ENOMEM if the device cannot hold the index. */
+int rambo_save(rambo_t *h, const char *path);
+rambo_t *rambo_load(const char *path);
 
 /* ---------------------------------------------------------------------- */
 /* Construction (Algorithm 1)                                              */

@@ -1,5 +1,6 @@
 // C ABI of librambo: handle lifetime, hash parameters, introspection, and
 // the entry points that validate arguments and dispatch to the kernels.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 
@@ -210,6 +211,7 @@ RAMBO_API int rambo_layout(const rambo_t *h, rambo_layout_t *out) {
     out->W = h->W;
     out->index_bytes = h->rows_bytes;
     out->rows = h->rows;
+    out->flags = h->opaque ? RAMBO_TERMS_OPAQUE : 0u;
     return RAMBO_OK;
 }
 
@@ -427,4 +429,162 @@ RAMBO_API int rambo_set_probe_counter(rambo_t *h, uint64_t *device_counter) {
     h->probe_counter = (unsigned long long *)device_counter;
     drop_graphs(h);
     return RAMBO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// index files
+// ---------------------------------------------------------------------------
+namespace {
+
+struct FileHeader {
+    char magic[8];  // "RAMBOIX1"
+    uint32_t version, header_bytes;
+    uint64_t K, m, seed, rows_bytes, checksum;
+    uint32_t B, R, eta, flags, row_words, reserved[5];
+};
+static_assert(sizeof(FileHeader) == 96, "index file header is 96 bytes");
+
+constexpr uint64_t kFileChunk = 64ull << 20;
+
+// The header's fields enter the checksum too (each through the same output
+// function as the row words, tagged by its place), so that a header altered
+// to other parameters -- which would derive other hash functions for the same
+// rows -- is refused as well.
+uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+uint64_t header_sum(const FileHeader &h) {
+    const uint64_t f[] = {h.K, h.m, h.seed, h.rows_bytes, h.B, h.R, h.eta, h.flags, h.row_words};
+    uint64_t s = 0;
+    for (uint64_t i = 0; i < sizeof f / sizeof f[0]; i++) s += mix64(f[i] ^ ((i + 1) << 56));
+    return s;
+}
+
+// Two pinned staging buffers and their events, freed on scope exit.
+struct Staging {
+    void *buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~Staging() {
+        for (int k = 0; k < 2; k++) {
+            if (ev[k]) (void)hipEventSynchronize(ev[k]);  // no copy still uses the buffer
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+            if (buf[k]) (void)hipHostFree(buf[k]);
+        }
+    }
+    int init() {
+        for (int k = 0; k < 2; k++) {
+            if (hipHostMalloc(&buf[k], kFileChunk) != hipSuccess) {
+                buf[k] = nullptr;
+                return fail(RAMBO_ENOMEM, "index file: cannot allocate pinned staging memory");
+            }
+            HIP_CHECK(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+        }
+        return RAMBO_OK;
+    }
+};
+
+struct File {
+    FILE *f = nullptr;
+    ~File() {
+        if (f) fclose(f);
+    }
+};
+
+}  // namespace
+
+RAMBO_API int rambo_save(rambo_t *h, const char *path) {
+    if (!h || !path) return fail(RAMBO_EINVAL, "rambo_save: null argument");
+    const hipStream_t s = h->aux;
+    HIP_CHECK(hipDeviceSynchronize());  // earlier inserts on any stream are complete
+    FileHeader hd{};
+    memcpy(hd.magic, "RAMBOIX1", 8);
+    hd.version = 1;
+    hd.header_bytes = sizeof(FileHeader);
+    hd.K = h->K; hd.m = h->m; hd.seed = h->seed; hd.rows_bytes = h->rows_bytes;
+    hd.B = h->B; hd.R = h->R; hd.eta = h->eta; hd.flags = h->opaque ? RAMBO_TERMS_OPAQUE : 0u;
+    hd.row_words = h->RW;
+    int st = rows_checksum(h, &hd.checksum, s);
+    if (st != RAMBO_OK) return st;
+    hd.checksum += header_sum(hd);
+    Staging sg;
+    if ((st = sg.init()) != RAMBO_OK) return st;
+    File fl;
+    fl.f = fopen(path, "wb");
+    if (!fl.f) return fail(RAMBO_EIO, "rambo_save: cannot open %s for writing", path);
+    if (fwrite(&hd, sizeof hd, 1, fl.f) != 1) return fail(RAMBO_EIO, "rambo_save: write failed (%s)", path);
+    // chunk k is copied into buffer k & 1 while chunk k - 1 is written out
+    const uint64_t n = (h->rows_bytes + kFileChunk - 1) / kFileChunk;
+    const char *src = reinterpret_cast<const char *>(h->rows);
+    for (uint64_t k = 0; k <= n; k++) {
+        if (k < n) {
+            const uint64_t len = std::min(kFileChunk, h->rows_bytes - k * kFileChunk);
+            HIP_CHECK(hipMemcpyAsync(sg.buf[k & 1], src + k * kFileChunk, len, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipEventRecord(sg.ev[k & 1], s));
+        }
+        if (k > 0) {
+            const uint64_t j = k - 1, len = std::min(kFileChunk, h->rows_bytes - j * kFileChunk);
+            HIP_CHECK(hipEventSynchronize(sg.ev[j & 1]));
+            if (fwrite(sg.buf[j & 1], 1, len, fl.f) != len)
+                return fail(RAMBO_EIO, "rambo_save: write failed (%s)", path);
+        }
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    FILE *f = fl.f;
+    fl.f = nullptr;
+    if (fclose(f) != 0) return fail(RAMBO_EIO, "rambo_save: write failed (%s)", path);
+    return ok();
+}
+
+RAMBO_API rambo_t *rambo_load(const char *path) {
+    if (!path) {
+        fail(RAMBO_EINVAL, "rambo_load: null path");
+        return nullptr;
+    }
+    File fl;
+    fl.f = fopen(path, "rb");
+    if (!fl.f) {
+        fail(RAMBO_EIO, "rambo_load: cannot open %s", path);
+        return nullptr;
+    }
+    FileHeader hd{};
+    if (fread(&hd, sizeof hd, 1, fl.f) != 1 || memcmp(hd.magic, "RAMBOIX1", 8) != 0 || hd.version != 1 ||
+        hd.header_bytes != sizeof(FileHeader)) {
+        fail(RAMBO_EIO, "rambo_load: %s is not a RAMBO index file (version 1)", path);
+        return nullptr;
+    }
+    rambo_t *h = rambo_create_ex(hd.K, hd.B, hd.R, hd.m, hd.eta, hd.seed, hd.flags);
+    if (!h) return nullptr;  // status and message from rambo_create_ex
+    auto drop = [&](int status, const char *msg) -> rambo_t * {
+        rambo_destroy(h);
+        fail(status, "rambo_load: %s (%s)", msg, path);
+        return nullptr;
+    };
+    if (h->rows_bytes != hd.rows_bytes || h->RW != hd.row_words) return drop(RAMBO_EIO, "row array size mismatch");
+    Staging sg;
+    if (sg.init() != RAMBO_OK) return drop(RAMBO_ENOMEM, "cannot allocate pinned staging memory");
+    // chunk k is read into buffer k & 1 while chunk k - 1 is copied up;
+    // before buffer k & 1 is refilled, the copy of chunk k - 2 from it ends
+    const hipStream_t s = h->aux;
+    if (hipDeviceSynchronize() != hipSuccess) return drop(RAMBO_EDEVICE, "device error");  // creation's zeroing
+    const uint64_t n = (h->rows_bytes + kFileChunk - 1) / kFileChunk;
+    char *dst = reinterpret_cast<char *>(h->rows);
+    for (uint64_t k = 0; k < n; k++) {
+        const uint64_t len = std::min(kFileChunk, h->rows_bytes - k * kFileChunk);
+        if (k >= 2 && hipEventSynchronize(sg.ev[k & 1]) != hipSuccess) return drop(RAMBO_EDEVICE, "copy failed");
+        if (fread(sg.buf[k & 1], 1, len, fl.f) != len) return drop(RAMBO_EIO, "file is shorter than its header says");
+        if (hipMemcpyAsync(dst + k * kFileChunk, sg.buf[k & 1], len, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipEventRecord(sg.ev[k & 1], s) != hipSuccess)
+            return drop(RAMBO_EDEVICE, "copy failed");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return drop(RAMBO_EDEVICE, "copy failed");
+    char extra;
+    if (fread(&extra, 1, 1, fl.f) != 0) return drop(RAMBO_EIO, "file is longer than its header says");
+    uint64_t sum = 0;
+    if (rows_checksum(h, &sum, s) != RAMBO_OK) return drop(RAMBO_EDEVICE, "checksum failed");
+    if (sum + header_sum(hd) != hd.checksum) return drop(RAMBO_EIO, "checksum mismatch: the file is corrupted");
+    ok();
+    return h;
 }

@@ -168,4 +168,51 @@ int launch_fold(rambo_s *h, const uint32_t *in, uint32_t *out, uint32_t RWi, uin
     return RAMBO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Checksum of the row array (index files): the sum, mod 2^64, of the
+// SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014) applied to
+// (word index << 32 | word) over every 32-bit word. Each term depends on a
+// word's value and place, so a changed, moved or missing word changes the sum
+// except with probability about 2^-64; the sum is independent of the order of
+// accumulation, so the grid adds its partial sums with atomics.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix_word(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_rows_checksum(const uint32_t *__restrict__ w, uint64_t n,
+                                                       unsigned long long *sum) {
+    uint64_t acc = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        acc += mix_word((i << 32) | w[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(sum, part[0] + part[1] + part[2] + part[3]);
+}
+
+int rows_checksum(rambo_s *h, uint64_t *out, hipStream_t s) {
+    unsigned long long *d = nullptr;
+    HIP_CHECK(hipMallocAsync((void **)&d, 8, s));
+    int st = RAMBO_OK;
+    if (hipMemsetAsync(d, 0, 8, s) != hipSuccess) st = fail(RAMBO_EDEVICE, "checksum: memset failed");
+    if (st == RAMBO_OK) {
+        hipLaunchKernelGGL(k_rows_checksum, dim3((unsigned)(h->n_cu * 8)), dim3(256), 0, s, h->rows,
+                           h->rows_bytes / 4, d);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(out, d, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = fail(RAMBO_EDEVICE, "checksum: launch or copy failed");
+    }
+    (void)hipFreeAsync(d, s);
+    (void)hipStreamSynchronize(s);
+    return st;
+}
+
 }  // namespace rambo

@@ -109,6 +109,8 @@ int launch_build_seqs(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, con
 int launch_dump_bfu(rambo_s *h, uint32_t r, uint32_t b, uint64_t *d_out, hipStream_t s);
 int launch_fold(rambo_s *h, const uint32_t *in, uint32_t *out, uint32_t RWi, uint32_t log2RWo, uint32_t half,
                 hipStream_t s);
+// Checksum of the row array (index files), synchronous on s.
+int rows_checksum(rambo_s *h, uint64_t *out, hipStream_t s);
 
 // query.hip
 int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *out, hipStream_t s);

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librambo.so")
 _lib = None
 
-OK, EINVAL, ENOMEM, EDEVICE, ETRUNC, EBUSY = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ETRUNC, EBUSY, EIO = 0, -1, -2, -3, -4, -5, -6
 MODE_PLAIN, MODE_BATCHED = 0, 1
 RESOLVE_AUTO, RESOLVE_DENSE, RESOLVE_CANDIDATE = 0, 1, 2
 TERMS_OPAQUE = 1
@@ -30,7 +30,7 @@ _u64, _u32, _i32, _vp, _cp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, cty
 
 class Layout(ctypes.Structure):
     _fields_ = [("K", _u64), ("m", _u64), ("seed", _u64), ("B", _u32), ("R", _u32), ("eta", _u32),
-                ("row_words", _u32), ("W", _u64), ("index_bytes", _u64), ("rows", _vp)]
+                ("row_words", _u32), ("W", _u64), ("index_bytes", _u64), ("rows", _vp), ("flags", _u32)]
 
 
 class TuneC(ctypes.Structure):
@@ -53,6 +53,8 @@ SIGNATURES = {
     "rambo_phi_table": ([_vp, _vp], _i32),
     "rambo_dump_bfu": ([_vp, _u32, _u32, _vp], _i32),
     "rambo_copy_rows": ([_vp, _u64, _u64, _vp], _i32),
+    "rambo_save": ([_vp, ctypes.c_char_p], _i32),
+    "rambo_load": ([ctypes.c_char_p], _vp),
     "rambo_fold": ([_vp], _i32),
     "rambo_insert": ([_vp, _u64, _vp, _u64], _i32),
     "rambo_insert_batch": ([_vp, _vp, _vp, _vp, _u64, _vp], _i32),
@@ -167,13 +169,32 @@ class Rambo:
         """opaque_terms: documents are sets of opaque 64-bit terms (word ids)
         instead of 31-mers; see rambo_create_ex."""
         L = lib()
-        self.opaque_terms = bool(opaque_terms)
-        self._h = L.rambo_create_ex(K, B, R, m, eta, seed, TERMS_OPAQUE if opaque_terms else 0)
-        if not self._h:
+        self._adopt(L.rambo_create_ex(K, B, R, m, eta, seed, TERMS_OPAQUE if opaque_terms else 0))
+
+    def _adopt(self, h):
+        if not h:
+            L = lib()
             raise RamboError(L.rambo_last_status(), L.rambo_last_error().decode(errors="replace"))
+        self._h = h
         lay = self.layout()
-        self.K, self.B, self.R, self.m, self.eta, self.seed = K, B, R, m, eta, seed
+        self.K, self.B, self.R, self.m = int(lay.K), int(lay.B), int(lay.R), int(lay.m)
+        self.eta, self.seed = int(lay.eta), int(lay.seed)
+        self.opaque_terms = bool(lay.flags & TERMS_OPAQUE)
         self.W, self.row_words, self.index_bytes = int(lay.W), int(lay.row_words), int(lay.index_bytes)
+
+    # -- index files
+    def save(self, path) -> None:
+        """Write the index to a file (header, then the row array; see rambo_save)."""
+        _check(lib().rambo_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path) -> "Rambo":
+        """An index read from a file written by save(), on the current GPU;
+        raises RamboError (status EIO) for a missing, foreign or corrupted file."""
+        obj = cls.__new__(cls)
+        obj._h = None
+        obj._adopt(lib().rambo_load(os.fsencode(path)))
+        return obj
 
     def close(self):
         if getattr(self, "_h", None):
