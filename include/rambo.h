@@ -221,7 +221,11 @@ int rambo_fold(rambo_t *h);
 
 /* n single k-mer queries (device array). out (device, n * W words) receives
  * one K-bit result per query. A value >= 4^31 gets an empty result and is
- * reported by rambo_sync(). Plain one-batch kernel. Enqueued on `stream`. */
+ * reported by rambo_sync(). Plain one-batch kernel. Enqueued on `stream`.
+ * With a NULL stream, kmers and out may instead both be host arrays: they
+ * are then copied in and out through device buffers the call allocates and
+ * frees, and the call returns when out holds the results (RAMBO_EINVAL if one
+ * array is on the host and the other on the device). */
 int rambo_query_kmers(rambo_t *h, const uint64_t *kmers, uint64_t n, uint64_t *out, void *stream);
 
 /* n sequence queries: read i is seqs[offsets[i] .. offsets[i+1]) (device

@@ -345,11 +345,44 @@ RAMBO_API int rambo_insert_seqs(rambo_t *h, const uint64_t *doc_ids, const uint8
 // ---------------------------------------------------------------------------
 // queries
 // ---------------------------------------------------------------------------
+// Memory the runtime does not know (pageable host memory) or host memory.
+static bool host_memory(const void *p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return a.type == hipMemoryTypeUnregistered || a.type == hipMemoryTypeHost;
+}
+
 RAMBO_API int rambo_query_kmers(rambo_t *h, const uint64_t *kmers, uint64_t n, uint64_t *out, void *stream) {
     if (!h) return fail(RAMBO_EINVAL, "rambo_query_kmers: null handle");
     if (n == 0) return RAMBO_OK;
     if (!kmers || !out) return fail(RAMBO_EINVAL, "rambo_query_kmers: null array");
-    return launch_query_kmers(h, kmers, n, out, (hipStream_t)stream);
+    if (stream != nullptr) return launch_query_kmers(h, kmers, n, out, (hipStream_t)stream);
+    const bool hk = host_memory(kmers), ho = host_memory(out);
+    if (!hk && !ho) return launch_query_kmers(h, kmers, n, out, nullptr);
+    if (!hk || !ho) return fail(RAMBO_EINVAL, "rambo_query_kmers: kmers and out must both be host or both device arrays");
+    // host arrays: synchronous copy in, query, copy out
+    const hipStream_t s = h->aux;
+    uint64_t *dk = nullptr, *dout = nullptr;
+    HIP_CHECK(hipMallocAsync((void **)&dk, n * 8, s));
+    int st = RAMBO_OK;
+    if (hipMallocAsync((void **)&dout, n * h->W * 8, s) != hipSuccess) {
+        (void)hipGetLastError();
+        dout = nullptr;
+        st = fail(RAMBO_ENOMEM, "rambo_query_kmers: cannot allocate %llu result bytes on the device",
+                  (unsigned long long)(n * h->W * 8));
+    }
+    if (st == RAMBO_OK && hipMemcpyAsync(dk, kmers, n * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        st = fail(RAMBO_EDEVICE, "rambo_query_kmers: copy in failed");
+    if (st == RAMBO_OK) st = launch_query_kmers(h, dk, n, dout, s);
+    if (st == RAMBO_OK && hipMemcpyAsync(out, dout, n * h->W * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = fail(RAMBO_EDEVICE, "rambo_query_kmers: copy out failed");
+    if (dout) (void)hipFreeAsync(dout, s);
+    (void)hipFreeAsync(dk, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == RAMBO_OK) st = fail(RAMBO_EDEVICE, "rambo_query_kmers: failed");
+    return st;
 }
 
 RAMBO_API int rambo_query_seqs(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n, uint64_t *out,

@@ -294,6 +294,16 @@ class Rambo:
                                            _stream(stream)))
         return out
 
+    def query_kmers_host(self, kmers) -> np.ndarray:
+        """Single k-mer queries from a host array (synchronous copy in and
+        out); returns a host [n][W] uint64 array."""
+        k = np.ascontiguousarray(kmers, dtype=np.uint64)
+        out = np.zeros((k.size, self.W), dtype=np.uint64)
+        if k.size:
+            _check(lib().rambo_query_kmers(self._h, ctypes.c_void_p(k.ctypes.data), k.size,
+                                           ctypes.c_void_p(out.ctypes.data), None))
+        return out
+
     def query_term_sets(self, terms, offsets, out=None, stream=None, check=True):
         """Term-set queries: set i is terms[offsets[i] .. offsets[i+1])
         (device int64 tensors); returns out [n][W]."""

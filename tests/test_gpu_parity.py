@@ -83,6 +83,18 @@ def test_c1_index_and_kmer_queries_bit_exact():
     # reverse-complemented queries give the same answers
     got = to_host_u64(idx.query_kmers(to_dev(_ref.revcomp_np(q))))
     assert np.array_equal(got, want)
+    # host arrays with no stream: synchronous copy in and out
+    assert np.array_equal(idx.query_kmers_host(q), want)
+    assert idx.query_kmers_host(q[:0]).shape == (0, idx.W)
+    # one host and one device array is refused
+    import ctypes
+    import torch
+    dq = to_dev(q)
+    hout = np.zeros((q.size, idx.W), dtype=np.uint64)
+    st = rb.lib().rambo_query_kmers(idx._h, ctypes.c_void_p(dq.data_ptr()), q.size,
+                                    ctypes.c_void_p(hout.ctypes.data), None)
+    assert st == rb.EINVAL
+    torch.cuda.synchronize()
     idx.close()
     idx2.close()
 
