@@ -37,7 +37,10 @@
  *    batch) are counted and reported by the next rambo_sync().
  *  - Queries may run concurrently on one handle. Insertions and queries must
  *    be ordered by the caller; a query that overlaps an insertion is
- *    unsupported.
+ *    unsupported. Batched-form queries with the same (seqs, offsets, n, out)
+ *    share one captured graph and its work-queue state, so calls that
+ *    overlap in time need distinct output buffers (they would write the same
+ *    output anyway).
  */
 #ifndef RAMBO_H
 #define RAMBO_H
