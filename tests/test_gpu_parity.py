@@ -321,3 +321,26 @@ def test_probe_counter_closed_form_without_early_exit(name):
     idx.set_probe_counter(None)
     idx.set_early_exit(True)
     idx.set_mode(rb.MODE_PLAIN)
+
+
+def test_concurrent_queries_on_two_streams():
+    """Queries may overlap on one handle: two streams, each with its own
+    output, both forms, give the oracle's answers."""
+    import torch
+    idx, o, dm, reads, want = setup_case("rw4")
+    seqs, offs = reads_to_dev(reads)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+        idx.set_mode(mode)
+        idx.query_seqs(seqs, offs)  # the batched form tunes once, outside the overlap
+        torch.cuda.synchronize()
+        outs = [torch.empty((reads.n, idx.W), dtype=torch.int64, device="cuda") for _ in streams]
+        for _ in range(3):
+            for st, out in zip(streams, outs):
+                st.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(st):
+                    idx.query_seqs(seqs, offs, out=out, stream=st, check=False)
+            torch.cuda.synchronize()
+            for out in outs:
+                assert np.array_equal(to_host_u64(out), want), mode
+    idx.set_mode(rb.MODE_PLAIN)
