@@ -294,8 +294,9 @@ def main():
                     help="time only one form (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (documents would be "
-              "sharded across GPUs with no exchange at build time; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (documents would be "
+              "sharded across GPUs, one independent index per GPU: no exchange at build time, one broadcast "
+              "of each read batch and one gather of the per-GPU result slices per query)", file=sys.stderr)
         sys.exit(2)
 
     import torch
