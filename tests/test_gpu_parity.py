@@ -344,3 +344,32 @@ def test_concurrent_queries_on_two_streams():
             for out in outs:
                 assert np.array_equal(to_host_u64(out), want), mode
     idx.set_mode(rb.MODE_PLAIN)
+
+
+def test_one_repetition_two_word_rows_one_hash():
+    """Unusual shapes: R = 1 (the scout windows are the only repetition-0
+    probes skipped later), rows of 2 words (B = 64), eta = 1; every schedule
+    in both forms against the oracle."""
+    K, B, R, m, eta, seed = 300, 64, 1, 1 << 18, 1, 4711
+    dm = gen.DocModel(seed=74, n_docs=K, length=5_000, docs_per_anc=30, mu_lo=0.01, mu_hi=0.01)
+    rm = gen.ReadModel(qseed=84, src_lo=0, src_hi=K, len_kind=0, median=300, sigma=1.0, lo=31, hi=3000,
+                       err_lo=0.0, err_hi=0.01)
+    idx = rb.Rambo(K, B, R, m, eta, seed)
+    build_gpu_seqs(idx, dm, 0, K)
+    o = build_oracle((K, B, R, m, eta, seed), dm)
+    reads = gen.reads(dm, rm, 800)
+    want, _ = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2, early_exit=True)
+    assert want.any(axis=1).sum() > 20
+    seqs, offs = reads_to_dev(reads)
+    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+        idx.set_mode(mode)
+        for ee in (True, False):
+            idx.set_early_exit(ee)
+            for sched in (0, 1, 2):
+                for tile in (64, 1024):
+                    t = idx.get_tune()
+                    t.sched, t.tile = sched, tile
+                    idx.set_tune(t)
+                    got = to_host_u64(idx.query_seqs(seqs, offs))
+                    assert np.array_equal(got, want), (mode, ee, sched, tile)
+    idx.close()
