@@ -1,15 +1,16 @@
-// Batched sequence queries: one persistent launch over a work queue of
-// (read, tile of windows) items, replayed from captured HIP graphs, with a
+// Batched sequence queries: a scout pass over every read (scout schedule),
+// then one persistent launch over a work queue of (read, tile of windows)
+// items of the reads still alive, replayed from captured HIP graphs, with a
 // launch shape chosen by an autotuner.
 //
-// Work order: first tile of every read, then the remaining tiles of all reads
-// in read order. Reads are short (a few hundred bases) and most end within
-// their first tile (Section 3.3.1: the first FALSE is conclusive), so later
-// tiles mostly find their read already dead and skip their probes. A read
-// that fits one tile is finished by the wave that took it, from registers.
-// Longer reads are spread over many waves; their tiles AND into a per-read
-// mask in global memory (AND is associative and commutative, so the order
-// does not matter) and the wave that finishes a read's last tile resolves it.
+// Most reads end on their scout windows (Section 3.3.1: the first FALSE is
+// conclusive); the scout pass answers them and leaves them out of the queue.
+// The queue runs longest work first (see the order below). A read that fits
+// one tile is finished by the wave that took it, from its LDS masks. Longer
+// reads are spread over many waves; their tiles AND into a per-read mask in
+// global memory (AND is associative and commutative, so the order does not
+// matter), a tile whose read is already dead skips its probes, and the wave
+// that finishes a read's last tile resolves it.
 //
 // The batch size lives in device memory, so one captured graph serves any
 // batch up to its capacity (the serving loop's slots rely on this).
