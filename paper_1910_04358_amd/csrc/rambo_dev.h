@@ -536,8 +536,13 @@ __device__ __forceinline__ StepBytes load_bytes(const uint8_t *__restrict__ seqs
 // over every step first, then the others over every step; a read whose answer
 // is empty (a random read, a read with a sequencing error) mostly ends within
 // repetition 0, without the other repetitions' rows for the windows before
-// its first mismatch. The next step's bytes are loaded while the current step
-// probes. Returns the number of (window, repetition) probes the wave issued.
+// its first mismatch. SCHED_SCOUT (with a staging area) first probes
+// repetition 0 on the span's scout windows, staged through LDS, then sweeps
+// as SCHED_SWEEP with those windows skipped in repetition 0; SCHED_PRESCOUT
+// sweeps the same way, skipping the scout windows of the whole read, which
+// the scout pass has probed and ANDed into M already. The next step's bytes
+// are loaded while the current step probes. Returns the number of (window,
+// repetition) probes the wave issued.
 template <int SEG, int G>
 __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t *__restrict__ seqs, uint64_t beg,
                                                   uint64_t end, uint64_t w_lo, uint64_t w_hi, uint32_t lane,
