@@ -158,7 +158,7 @@ class Tune:
     waves_per_cu: int
     wpb: int
     grab: int
-    sched: int = 0
+    sched: int = 2  # the library's default: scout schedule
     tuned: bool = False
 
 

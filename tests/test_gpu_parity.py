@@ -180,9 +180,20 @@ def test_edge_case_reads():
         assert np.array_equal(wantc[i], everyone)
     for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
         idx.set_mode(mode)
-        idx.set_tune(rb.Tune(4, 64, 8, 4, 1))
-        got = to_host_u64(idx.query_seqs(to_dev(seqs), to_dev(offs)))
-        assert np.array_equal(got, wantc), mode
+        for sched in (0, 1, 2):
+            for tile in (64, 1024):
+                idx.set_tune(rb.Tune(4, tile, 8, 4, 1, sched))
+                got = to_host_u64(idx.query_seqs(to_dev(seqs), to_dev(offs)))
+                assert np.array_equal(got, wantc), (mode, sched, tile)
+                ids, id_off = idx.query_seqs_ids(to_dev(seqs), to_dev(offs), ids_cap=idx.K * len(cases))
+                ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
+                for i in range(len(cases)):
+                    assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(wantc[i], idx.K))
+        # an empty batch
+        e_seqs, e_offs = make_reads([])
+        assert idx.query_seqs(to_dev(e_seqs), to_dev(e_offs)).shape[0] == 0
+        ids, id_off = idx.query_seqs_ids(to_dev(e_seqs), to_dev(e_offs), ids_cap=0)
+        assert ids.numel() == 0 and id_off.cpu().tolist() == [0]
     idx.set_mode(rb.MODE_PLAIN)
 
 
