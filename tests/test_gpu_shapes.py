@@ -3,7 +3,8 @@ two-row-word split and past 1,024 (rows of 1 to 64 words), R from 1 to 8,
 eta from 1 to 5 (the generic row loop above 3), m not a power of two (the
 multiply-high range reduction), K not a multiple of 64 (result padding).
 Every shape: the whole index against the oracle's bits on sampled BFUs, and
-every read in both forms and every resolve strategy against the oracle."""
+every read in both forms, every resolve strategy and schedule, with and
+without early exit, against the oracle."""
 import numpy as np
 import pytest
 
@@ -47,9 +48,16 @@ def test_unusual_shapes_bit_exact(shape):
         idx.set_mode(mode)
         for resolve in (rb.RESOLVE_AUTO, rb.RESOLVE_DENSE, rb.RESOLVE_CANDIDATE):
             idx.set_resolve(resolve)
-            got = to_host_u64(idx.query_seqs(seqs, offs))
-            bad = np.nonzero((got != want).any(axis=1))[0]
-            assert bad.size == 0, (mode, resolve, bad[:5])
+            for ee in (True, False):
+                idx.set_early_exit(ee)
+                for sched in (0, 1, 2):
+                    t = idx.get_tune()
+                    t.sched = sched
+                    idx.set_tune(t)
+                    got = to_host_u64(idx.query_seqs(seqs, offs))
+                    bad = np.nonzero((got != want).any(axis=1))[0]
+                    assert bad.size == 0, (mode, resolve, ee, sched, bad[:5])
+    idx.set_early_exit(True)
     # single k-mer queries as well
     q, _ = gen.kmer_queries(dm, B + 2, 500, 0.5)
     idx.set_resolve(rb.RESOLVE_AUTO)
