@@ -63,3 +63,36 @@ def test_unusual_shapes_bit_exact(shape):
     idx.set_resolve(rb.RESOLVE_AUTO)
     assert np.array_equal(idx.query_kmers_host(q), o.query_kmers(q))
     idx.close()
+
+
+@pytest.mark.parametrize("shape", [(640, 300, 3, 1 << 19, 2), (900, 2048, 2, 400_009, 3)],
+                         ids=lambda s: "K%d-B%d" % s[:2])
+def test_streaming_then_fold_wide_rows(shape):
+    """Half the documents, then the rest streamed into the resident index
+    (equal to the oracle's build of all), then two folds (rows shrink from 16
+    to 4 words, or 64 to 16): every sampled BFU and every read equal the
+    oracle's fold."""
+    K, B, R, m, eta = shape
+    seed = 9100 + B
+    dm = gen.DocModel(seed=B + 7, n_docs=K, length=3_000, docs_per_anc=10, mu_lo=0.01, mu_hi=0.01)
+    rm = gen.ReadModel(qseed=B + 8, src_lo=0, src_hi=K, len_kind=0, median=200, sigma=0.8, lo=31, hi=2_000,
+                       err_lo=0.0, err_hi=0.01)
+    idx = rb.Rambo(K, B, R, m, eta, seed)
+    build_gpu_seqs(idx, dm, 0, K // 2)
+    build_gpu_seqs(idx, dm, K // 2, K - K // 2)
+    o = build_oracle((K, B, R, m, eta, seed), dm)
+    reads = gen.reads(dm, rm, 300)
+    seqs, offs = reads_to_dev(reads)
+    rng = np.random.default_rng(B)
+    for _ in range(2):
+        idx.fold()
+        o = o.fold()
+        assert idx.B == o.B
+        bits = o.bits()
+        for r, b in {(int(rng.integers(R)), int(rng.integers(idx.B))) for _ in range(10)}:
+            assert np.array_equal(idx.dump_bfu(r, b), bits[r, b]), (idx.B, r, b)
+        want, _ = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2)
+        for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+            idx.set_mode(mode)
+            assert np.array_equal(to_host_u64(idx.query_seqs(seqs, offs)), want), (idx.B, mode)
+    idx.close()
