@@ -90,6 +90,11 @@ __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t
     }
 }
 
+// lanes per read in the scout pass
+__host__ __device__ constexpr int scout_group(int G, bool narrow) {
+    return (narrow && G >= 8) ? (4 * G < 64 ? 4 * G : 64) : (16 * G < 64 ? 16 * G : 64);
+}
+
 // Scout pass of the batched form (SCHED_SCOUT), before the queue is
 // built: repetition 0 on every read's scout windows (every 31st window and
 // the last, which together cover every base of the read). A group of GS
@@ -101,11 +106,14 @@ __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t
 // in id-list mode) is written now and the read never enters the queue. The
 // grid (up to 8 workgroups per CU, striding over the reads) keeps thousands
 // of reads in flight, which hides the latency of these few dependent steps; a
-// wave of the persistent kernel pays it in full, read by read.
-template <int SEG, int G>
+// wave of the persistent kernel pays it in full, read by read. NARROW (id-list
+// mode, where an ended read costs no output) gives rows split over 8 or more
+// lanes 4 windows per round instead of 8: a finer early exit for fewer probes;
+// with bitsets the wider groups write the zero bitsets faster.
+template <int SEG, int G, int NARROW>
 __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *in, uint64_t *__restrict__ out,
                                                      BatchBufs bb, QueryOpts opt) {
-    constexpr int GS = (16 * G < 64) ? 16 * G : 64;  // lanes per read
+    constexpr int GS = scout_group(G, NARROW != 0);  // lanes per read
     constexpr int SLOTS = GS / G;                   // windows per round
     const uint8_t *__restrict__ seqs = in->seqs;
     const uint64_t *__restrict__ offs = in->offs;
@@ -329,11 +337,17 @@ static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
         const Index ix = make_index(h);
         const int G = (int)h->RW / tu.seg;
         // a grid of at most 8 workgroups per CU strides over the reads
-        const uint64_t GS = std::min(64, 16 * G);
+        const bool narrow = counts != nullptr;
+        const uint64_t GS = (uint64_t)scout_group(G, narrow);
         const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((bg.cap * GS + 255) / 256, 8ull * h->n_cu));
         QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched, counts};
 #define RAMBO_SPLIT_BODY_                                                                                   \
-    hipLaunchKernelGGL((k_batch_scout<SEG, G>), dim3((unsigned)blocks), dim3(256), 0, s, ix, bg.in, out, bg.bb, opt)
+    if (narrow)                                                                                             \
+        hipLaunchKernelGGL((k_batch_scout<SEG, G, 1>), dim3((unsigned)blocks), dim3(256), 0, s, ix, bg.in, out,   \
+                           bg.bb, opt);                                                                      \
+    else                                                                                                     \
+        hipLaunchKernelGGL((k_batch_scout<SEG, G, 0>), dim3((unsigned)blocks), dim3(256), 0, s, ix, bg.in, out,   \
+                           bg.bb, opt)
         RAMBO_DISPATCH_SPLIT(tu.seg, G)
 #undef RAMBO_SPLIT_BODY_
         HIP_CHECK(hipGetLastError());
