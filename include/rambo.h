@@ -34,7 +34,8 @@
  *  - Every entry point returns a status (RAMBO_OK = 0, negative on error)
  *    and records a message readable with rambo_last_error() on the calling
  *    thread. Errors detected on the GPU (invalid k-mer values in a device
- *    batch) are counted and reported by the next rambo_sync().
+ *    batch) are counted and reported by the next rambo_sync(), and so are
+ *    queries that hold no term (RAMBO_OK_EMPTYQ, not an error).
  *  - Queries may run concurrently on one handle. Insertions and queries must
  *    be ordered by the caller; a query that overlaps an insertion is
  *    unsupported. Batched-form queries with the same (seqs, offsets, n, out)
@@ -56,6 +57,10 @@ typedef struct rambo_s rambo_t;
 
 enum {
     RAMBO_OK = 0,
+    RAMBO_OK_EMPTYQ = 1, /* success; some query held no term (a read with no
+                            valid 31-window, an empty term set) and was
+                            answered with every document, the vacuous
+                            "every term of Q is in the BFU" of Algorithm 2 */
     RAMBO_EINVAL = -1,  /* bad argument or invalid k-mer value */
     RAMBO_ENOMEM = -2,  /* device or host allocation failed */
     RAMBO_EDEVICE = -3, /* HIP runtime error */
@@ -81,10 +86,13 @@ enum {
                                     are tested in the other repetitions */
 };
 
-/* Limits: 1 <= R <= 8, 1 <= eta <= 8, 1 <= B <= 8192, 1 <= K < 2^32,
- * 1 <= m <= 2^40. */
+/* Limits: 1 <= R <= 8, 1 <= eta <= 16, 1 <= B <= 8192, 1 <= K < 2^32,
+ * 1 <= m <= 2^40. R and B are bounded by the layout: a document's cells are
+ * one 16-byte record (R 16-bit slots), and a query keeps R masks of B bits
+ * per wave in LDS while a row of B bits is read by at most 64 lanes x 16
+ * bytes in one load instruction. */
 #define RAMBO_MAX_R 8
-#define RAMBO_MAX_ETA 8
+#define RAMBO_MAX_ETA 16
 #define RAMBO_MAX_B 8192
 
 /* ---------------------------------------------------------------------- */
@@ -123,9 +131,12 @@ const char *rambo_last_error(void);
 int rambo_last_status(void);
 
 /* Wait for all work the handle enqueued on `stream` (NULL: the null stream)
- * and report GPU-side input errors counted since the previous call:
- * RAMBO_EINVAL if any k-mer value >= 4^31 was skipped by an insertion or
- * answered with an empty result by a query. */
+ * and report what the GPU counted since the previous call: RAMBO_EINVAL if
+ * any k-mer value >= 4^31 (or document id >= K) was skipped by an insertion
+ * or answered with an empty result by a query; otherwise RAMBO_OK_EMPTYQ if
+ * a sequence or term-set query (rambo_query_seqs, rambo_query_term_sets, the
+ * server's batches) held no term; otherwise RAMBO_OK. The counters belong to
+ * the handle: work on other streams that ran meanwhile is counted too. */
 int rambo_sync(rambo_t *h, void *stream);
 
 /* ---------------------------------------------------------------------- */
@@ -235,9 +246,10 @@ int rambo_query_kmers(rambo_t *h, const uint64_t *kmers, uint64_t n, uint64_t *o
  * arrays; offsets non-decreasing). out (device, n * W words) receives, per
  * read, the documents that hold every term of the read. A read with no valid
  * window gets every document (the vacuous "every term is in the BFU" of
- * Algorithm 2). Once the running AND of some repetition is empty the read is
- * finished (Section 3.3.1: the first FALSE is conclusive). Uses the handle's
- * mode (rambo_set_mode). Enqueued on `stream`. */
+ * Algorithm 2) and is counted for rambo_sync (RAMBO_OK_EMPTYQ). Once the
+ * running AND of some repetition is empty the read is finished: no later
+ * term can bring a document back (Section 3.3.1). Uses the handle's mode
+ * (rambo_set_mode). Enqueued on `stream`. */
 int rambo_query_seqs(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
                      uint64_t *out, void *stream);
 
@@ -248,7 +260,8 @@ int rambo_query_seqs(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, u
  * (Algorithm 2). On a k-mer index the values are 2-bit 31-mer codes of either
  * strand; a query holding a value >= 4^31 answers no document and is counted
  * as invalid (reported by rambo_sync). On an opaque-term index any value is a
- * term. An empty set answers every document. Device arrays (offsets n + 1
+ * term. An empty set answers every document (counted for rambo_sync as
+ * RAMBO_OK_EMPTYQ). Device arrays (offsets n + 1
  * words, non-decreasing; out n * W words as rambo_query_kmers), asynchronous
  * on `stream`; one wave per set, repetition 0 over all terms before the
  * others; the resolve and early exit settings apply. */
@@ -263,8 +276,10 @@ int rambo_query_term_sets(rambo_t *h, const uint64_t *terms, const uint64_t *off
  * the bitset traffic of the many empty answers. Synchronous on `stream` (it
  * must learn the total). If the total exceeds ids_cap, returns RAMBO_ETRUNC
  * with id_offsets filled (id_offsets[n] = required capacity) and ids
- * untouched. Calls on one handle are serialised (a per-handle buffer holds
- * the answer sizes). */
+ * untouched. Returns RAMBO_OK_EMPTYQ instead of RAMBO_OK if some read had no
+ * valid window (its list holds every document). Calls on one handle are
+ * serialised (a per-handle buffer holds the answer sizes, allocated or grown
+ * by the call when n exceeds every earlier n). */
 int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
                          uint64_t *scratch, uint32_t *ids, uint64_t *id_offsets, uint64_t ids_cap,
                          void *stream);

@@ -168,10 +168,11 @@ RAMBO_API rambo_t *rambo_create_ex(uint64_t K, uint32_t B, uint32_t R, uint64_t 
     int st = RAMBO_OK;
     if (hipMemset(h->rows, 0, h->rows_bytes) != hipSuccess) st = fail(RAMBO_EDEVICE, "rambo_create: memset failed");
     if (st == RAMBO_OK) st = upload_tables(h);
-    if (st == RAMBO_OK && hipMalloc(&h->d_invalid, sizeof(unsigned long long)) != hipSuccess)
+    if (st == RAMBO_OK && hipMalloc(&h->d_invalid, 2 * sizeof(unsigned long long)) != hipSuccess)
         st = fail(RAMBO_ENOMEM, "rambo_create: counter allocation failed");
-    if (st == RAMBO_OK && hipMemset(h->d_invalid, 0, sizeof(unsigned long long)) != hipSuccess)
+    if (st == RAMBO_OK && hipMemset(h->d_invalid, 0, 2 * sizeof(unsigned long long)) != hipSuccess)
         st = fail(RAMBO_EDEVICE, "rambo_create: memset failed");
+    if (st == RAMBO_OK) h->d_emptyq = h->d_invalid + 1;
     if (st == RAMBO_OK && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess)
         st = fail(RAMBO_EDEVICE, "rambo_create: stream creation failed");
     if (st != RAMBO_OK) {
@@ -194,13 +195,11 @@ RAMBO_API int rambo_sync(rambo_t *h, void *stream) {
     if (!h) return fail(RAMBO_EINVAL, "rambo_sync: null handle");
     hipStream_t s = (hipStream_t)stream;
     HIP_CHECK(hipStreamSynchronize(s));
-    unsigned long long bad = 0;
-    HIP_CHECK(hipMemcpy(&bad, h->d_invalid, sizeof bad, hipMemcpyDeviceToHost));
-    if (bad) {
-        HIP_CHECK(hipMemset(h->d_invalid, 0, sizeof bad));
-        return fail(RAMBO_EINVAL, "%llu invalid k-mer values or document ids were skipped", bad);
-    }
-    return RAMBO_OK;
+    unsigned long long c[2] = {0, 0};  // invalid inputs, queries without a term
+    HIP_CHECK(hipMemcpy(c, h->d_invalid, sizeof c, hipMemcpyDeviceToHost));
+    if (c[0] || c[1]) HIP_CHECK(hipMemset(h->d_invalid, 0, sizeof c));
+    if (c[0]) return fail(RAMBO_EINVAL, "%llu invalid k-mer values or document ids were skipped", c[0]);
+    return c[1] ? RAMBO_OK_EMPTYQ : RAMBO_OK;
 }
 
 RAMBO_API int rambo_layout(const rambo_t *h, rambo_layout_t *out) {
@@ -420,12 +419,14 @@ RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64
         h->d_ids_counts = nullptr;
         h->d_ids_aux = nullptr;
         h->ids_counts_cap = 0;
-        HIP_CHECK(hipMalloc(&h->d_ids_counts, n * 8));
+        HIP_CHECK(hipMalloc(&h->d_ids_counts, (n + 1) * 8));
         HIP_CHECK(hipMalloc(&h->d_ids_aux, ids_aux_words(n) * 8));
         h->ids_counts_cap = n;
     }
     const hipStream_t s = (hipStream_t)stream;
-    int st = h->mode == RAMBO_MODE_BATCHED
+    int st = launch_store_u64(reinterpret_cast<uint64_t *>(h->d_ids_counts) + n, 0, s);  // reads without a term
+    if (st != RAMBO_OK) return st;
+    st = h->mode == RAMBO_MODE_BATCHED
                  ? query_seqs_batched(h, seqs, offsets, n, scratch, s, h->d_ids_counts)
                  : launch_query_seqs_plain(h, seqs, offsets, n, scratch, s, default_seg(h->RW), nullptr,
                                            h->d_ids_counts);

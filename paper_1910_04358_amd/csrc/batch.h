@@ -9,14 +9,16 @@ namespace rambo {
 
 struct BatchBufs {
     uint32_t *rmask;           // [cap][R * RW] running AND per multi-tile read
-    uint32_t *done;            // [cap] finished tiles per multi-tile read
+    unsigned long long *done;  // [cap] per multi-tile read: finished tiles (low 32 bits) and
+                               // finished tiles that held a valid window (high 32 bits)
     uint64_t *extra;           // [cap] tiles beyond the first, per read
     uint64_t *extra_off;       // [cap + 1] exclusive scan of extra
     uint32_t *order;           // [4][cap] reads by size class of their first tile
     unsigned long long *cls;   // reads of size class v at cls[16 v]
     unsigned long long *head;  // queue position
     uint32_t *smask;           // [cap][RW] repetition-0 AND over the scout windows (SCHED_PRESCOUT)
-    uint32_t *live;            // [cap] read not ended by the scout pass (SCHED_PRESCOUT)
+    uint32_t *live;            // [cap] bit 0: read not ended by the scout pass; bit 1: a scout
+                               // window was valid (SCHED_PRESCOUT)
     uint64_t cap;
 };
 

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t
     const uint32_t lane = threadIdx.x & 63;
     bool real = i < n;
     uint32_t cls = 0;
-    if (real && prescout && !bb.live[i]) {
+    if (real && prescout && !(bb.live[i] & 1u)) {
         bb.extra[i] = 0;
         real = false;
     } else if (real) {
@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
         Seg<SEG> acc;
 #pragma unroll
         for (int s = 0; s < SEG; s++) acc.w[s] = 0xFFFFFFFFu;
-        bool live = true;  // uniform over the group
+        bool live = true;   // uniform over the group
+        bool saw = false;   // some scout window was valid (uniform over the group)
         for (uint64_t k0 = 0;; k0 += SLOTS) {
             const bool active = live && k0 < ns;
             if (__ballot(active) == 0) break;
@@ -151,7 +152,9 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
 #pragma unroll
             for (int s = 0; s < SEG; s++) cm[0].w[s] = 0xFFFFFFFFu;
             if (wv.valid) probe_reps<SEG, 0, 1>(ix, ix.hp->h, wv.canon, seg, cm);
-            issued += (uint64_t)__popcll(__ballot(wv.valid && seg == 0));
+            const uint64_t vb = __ballot(wv.valid && seg == 0);
+            issued += (uint64_t)__popcll(vb);
+            saw |= (vb & gmask) != 0;
             uint32_t o = 0;
 #pragma unroll
             for (int s = 0; s < SEG; s++) {
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
             if (slot == 0)
 #pragma unroll
                 for (int s = 0; s < SEG; s++) bb.smask[i * ix.RW + seg * SEG + s] = acc.w[s];
-            if (sub == 0) bb.live[i] = live ? 1u : 0u;
+            if (sub == 0) bb.live[i] = (live ? 1u : 0u) | (saw ? 2u : 0u);
             if (!live) {
                 if (opt.counts) {
                     if (sub == 0) opt.counts[i] = 0;
@@ -278,40 +281,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
             init_masks(ix, M, lane);
             if (opt.sched == SCHED_PRESCOUT && ntiles == 1)
                 for (uint32_t w = lane; w < ix.RW; w += 64) M[w] = bb.smask[i * ix.RW + w];
+            uint64_t got = 0;  // probes this item issued (0: no valid window in it)
             if (!skip) {
                 const uint64_t w_hi = min(nwin, (c + 1) * (uint64_t)tile);
-                issued += probe_windows<SEG, G>(ix, seqs, beg, end, c * (uint64_t)tile, w_hi, lane, M,
-                                                opt.early_exit != 0, opt.sched, stage);
+                got = probe_windows<SEG, G>(ix, seqs, beg, end, c * (uint64_t)tile, w_hi, lane, M,
+                                            opt.early_exit != 0, opt.sched, stage);
+                issued += got;
             }
+            // a scout window of the read was valid (it was probed by the scout pass)
+            const bool scout_saw = opt.sched == SCHED_PRESCOUT && (bb.live[i] & 2u);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (ntiles == 1) {
                 // the whole read was in this tile: resolve from its masks
+                if (got == 0 && !scout_saw && lane == 0) atomicAdd(opt.emptyq, 1ULL);
                 answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, i);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 continue;
             }
-            // Publish this tile's masks, then count the tile done. Both are
-            // agent-scope atomic read-modify-writes, performed at the point
-            // of coherence of all XCDs; the workgroup-scope fence between them
-            // makes the wave wait for the ANDs to complete before it counts
-            // (no L2 write-back is needed: nothing here is a plain store).
+            // Publish this tile's masks, then count the tile done. Every
+            // access to rm and done is an agent-scope atomic read-modify-write,
+            // performed at the device's point of coherence (one for all XCDs),
+            // and a returning RMW's old value comes back only once the RMW has
+            // been performed there. The ANDs return their old values, the
+            // wave folds them into one value (a ballot over every lane's
+            // results) and the count's operand is made to depend on it, so
+            // the count is issued only after each of this tile's ANDs has
+            // been performed. The last tile issues its mask reads only after
+            // its own count has returned, i.e. after every other tile's count
+            // and hence after every other tile's ANDs. (A release fence at
+            // agent scope would also order them, but on a multi-XCD device it
+            // writes back the XCD's whole L2, which made small tiles 4.5x
+            // slower; nothing here needs it, as no plain store is published.)
+            uint32_t olds = 0;
             if (!skip) {
                 for (uint32_t w = lane; w < mw; w += 64) {
                     const uint32_t v = M[w];
                     if (v != 0xFFFFFFFFu)
-                        __hip_atomic_fetch_and(rm + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        olds |= __hip_atomic_fetch_and(rm + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            uint32_t prev = 0;
-            if (lane == 0) prev = __hip_atomic_fetch_add(bb.done + i, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            prev = __builtin_amdgcn_readfirstlane(__shfl(prev, 0));
-            if (prev + 1 == ntiles) {
-                // last tile of read i: every other tile's ANDs were performed
-                // before its count; read the masks with atomic RMWs as well
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            // (a skipped tile belongs to a read whose answer is empty anyway:
+            // it counts as holding a valid window)
+            const unsigned long long inc = 1ull + ((got > 0 || skip) ? (1ull << 32) : 0ull);
+            const uint32_t zero = opaque_zero(__ballot(olds != 0));
+            unsigned long long prev = 0;
+            if (lane == 0)
+                prev = __hip_atomic_fetch_add(bb.done + i, inc + zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            prev = uniform64(__shfl(prev, 0));
+            if ((prev & 0xFFFFFFFFull) + 1 == ntiles) {
+                if ((prev >> 32) + (inc >> 32) == 0 && !scout_saw && lane == 0) atomicAdd(opt.emptyq, 1ULL);
+                // last tile of read i: read the masks with atomic RMWs too,
+                // at the same point of coherence as the ANDs
                 for (uint32_t w = lane; w < mw; w += 64)
                     M[w] = __hip_atomic_fetch_or(rm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -340,7 +362,8 @@ static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
         const bool narrow = counts != nullptr;
         const uint64_t GS = (uint64_t)scout_group(G, narrow);
         const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((bg.cap * GS + 255) / 256, 8ull * h->n_cu));
-        QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched, counts};
+        QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched, counts,
+                      counts ? counts + bg.cap : h->d_emptyq};
 #define RAMBO_SPLIT_BODY_                                                                                   \
     if (narrow)                                                                                             \
         hipLaunchKernelGGL((k_batch_scout<SEG, G, 1>), dim3((unsigned)blocks), dim3(256), 0, s, ix, bg.in, out,   \
@@ -372,7 +395,7 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
     }
     // the scout schedule has run its scout windows in the scout pass already
     const int ksched = tu.sched == SCHED_SCOUT ? SCHED_PRESCOUT : tu.sched;
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, ksched, counts};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, ksched, counts, counts ? counts + bg.cap : h->d_emptyq};
     // a persistent grid must be resident: never more workgroups than fit
 #define RAMBO_SPLIT_BODY_                                                                                  \
     {                                                                                                      \
@@ -424,7 +447,7 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
         b_smask = al(cap * h->RW * 4);
         b_live = al(cap * 4);
         b_mask = al(cap * mw * 4);
-        b_done = al(cap * 4);
+        b_done = al(cap * 8);
         b_extra = al(cap * 8);
         b_off = al((cap + 1) * 8);
         b_parts = al(scan_parts_needed(cap) * 8);
@@ -436,7 +459,7 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
     bg.bb.live = b_live ? (uint32_t *)p : nullptr; p += b_live;
     bg.parts = (uint64_t *)p; p += b_parts;
     bg.bb.rmask = (uint32_t *)p; p += b_mask;
-    bg.bb.done = (uint32_t *)p; p += b_done;
+    bg.bb.done = (unsigned long long *)p; p += b_done;
     bg.bb.extra = (uint64_t *)p; p += b_extra;
     bg.bb.extra_off = (uint64_t *)p; p += b_off;
     bg.bb.order = (uint32_t *)p; p += b_order;

@@ -188,6 +188,9 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
     const uint64_t issued =
         probe_windows<SEG, G>(ix, seqs, beg, end, 0, nwin, lane, M, opt.early_exit != 0, opt.sched, stage);
     if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
+    // every valid window is probed at least in repetition 0 unless a probe
+    // has ended the read first, so nothing issued means no valid window
+    if (issued == 0 && lane == 0) atomicAdd(opt.emptyq, 1ULL);
     uint64_t *o = out + read * ix.W;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -216,6 +219,7 @@ __global__ __launch_bounds__(256) void k_query_termsets(Index ix, const uint64_t
     if (end < beg) end = beg;
     const uint64_t len = end - beg;
     uint64_t *o = out + q * ix.W;
+    if (len == 0 && lane == 0) atomicAdd(opt.emptyq, 1ULL);
 
     // a k-mer index takes 31-mer codes only: a set holding another value
     // answers no document
@@ -309,7 +313,9 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     }
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, sched, counts};
+    // id-list mode counts queries without a term in the word after the n
+    // answer sizes (the caller zeroes it), bitset mode in the handle
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, sched, counts, counts ? counts + n : h->d_emptyq};
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
                        n, hdr, out, opt, use_res)
@@ -332,7 +338,7 @@ int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *off
     }
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_term_sets: batch too large");
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, SCHED_SWEEP, nullptr};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, SCHED_SWEEP, nullptr, h->d_emptyq};
 #define RAMBO_SPLIT_BODY_                                                                                  \
     hipLaunchKernelGGL((k_query_termsets<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, terms, offs, \
                        n, out, opt, use_res, h->d_invalid)
@@ -400,7 +406,9 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
     HIP_CHECK(hipGetLastError());
     int sst = launch_exclusive_scan(reinterpret_cast<const uint64_t *>(counts), d_n, n, id_off, parts, s);
     if (sst != RAMBO_OK) return sst;
+    unsigned long long noterm = 0;
     hipError_t e = hipMemcpyAsync(&total, id_off + n, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && counts) e = hipMemcpyAsync(&noterm, counts + n, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(RAMBO_EDEVICE, "rambo_query_seqs_ids: %s", hipGetErrorString(e));
     if (total > ids_cap)
@@ -413,6 +421,12 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
         HIP_CHECK(hipGetLastError());
     }
     HIP_CHECK(hipStreamSynchronize(s));
+    return noterm ? RAMBO_OK_EMPTYQ : RAMBO_OK;
+}
+
+int launch_store_u64(uint64_t *p, uint64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_store_u64, dim3(1), dim3(64), 0, s, p, v);
+    HIP_CHECK(hipGetLastError());
     return RAMBO_OK;
 }
 

@@ -14,7 +14,7 @@
 namespace rambo {
 
 constexpr int MAXR = 8;
-constexpr int MAXETA = 8;
+constexpr int MAXETA = 16;
 constexpr uint64_t MASK62 = (1ULL << 62) - 1;
 
 // Bloom hash parameters h_{r,j} (A = ahi:alo, C = chi:clo), index
@@ -444,6 +444,16 @@ __device__ __forceinline__ bool probe_group(const Index &ix, const HashRec *hp, 
     for (int k = 0; k < COUNT; k++)
         if (FIRST + k < (int)ix.R) alive &= fold_rep<SEG, G>(cm[k], M + (FIRST + k) * ix.RW, lane);
     return alive;
+}
+
+// Zero, as a value the compiler cannot see through: it depends on x, so an
+// operation that takes it as an operand is issued only once x is available
+// (when x comes from the results of loads or atomics, once they have
+// returned).
+__device__ __forceinline__ uint32_t opaque_zero(uint64_t x) {
+    uint32_t z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z) : "s"(x));
+    return z;
 }
 
 // Probe schedules of a read's windows (all give the same running masks)

@@ -59,7 +59,8 @@ struct rambo_s {
     rambo::HashParams *d_hp = nullptr;
     uint4 *d_cells = nullptr;  // [K] phi_r(d) of every repetition, 16 bits each
     uint32_t *d_boff = nullptr, *d_bdoc = nullptr;
-    unsigned long long *d_invalid = nullptr;
+    unsigned long long *d_invalid = nullptr;  // [2]: invalid inputs, queries without a term
+    unsigned long long *d_emptyq = nullptr;   // = d_invalid + 1
     std::vector<uint64_t> pa, pb, Alo, Ahi, Clo, Chi;
     std::vector<uint32_t> phi;  // [R][K]
     int mode = RAMBO_MODE_PLAIN, resolve = RAMBO_RESOLVE_AUTO, early_exit = 1;
@@ -99,6 +100,7 @@ struct QueryOpts {
     unsigned long long *probes;   // may be null
     int sched;                    // probe schedule (SCHED_*)
     unsigned long long *counts;   // id-list mode: per-read answer sizes, zero answers not written; or null
+    unsigned long long *emptyq;   // incremented once per query that has no term (no valid window)
 };
 
 // build.hip
@@ -124,8 +126,12 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
 // Bitsets of an id-list mode query to id lists: counts holds the n answer
 // sizes the query wrote, aux ids_aux_words(n) words of scan scratch.
 uint64_t ids_aux_words(uint64_t n);
+// counts has n + 1 words: the answer sizes, then the number of reads without
+// a term (RAMBO_OK_EMPTYQ is returned if it is not zero).
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off,
                uint64_t ids_cap, hipStream_t s, const unsigned long long *counts, uint64_t *aux);
+// *p = v on stream s (a one-thread kernel: no memset node in captured work)
+int launch_store_u64(uint64_t *p, uint64_t v, hipStream_t s);
 
 // batch.hip
 int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,

@@ -19,10 +19,11 @@ LIB_PATH = os.path.join(_HERE, "librambo.so")
 _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, ETRUNC, EBUSY, EIO = 0, -1, -2, -3, -4, -5, -6
+OK_EMPTYQ = 1  # success; some query held no term (answered with every document)
 MODE_PLAIN, MODE_BATCHED = 0, 1
 RESOLVE_AUTO, RESOLVE_DENSE, RESOLVE_CANDIDATE = 0, 1, 2
 TERMS_OPAQUE = 1
-MAX_R, MAX_ETA, MAX_B = 8, 8, 8192
+MAX_R, MAX_ETA, MAX_B = 8, 16, 8192
 
 # every function the C ABI exports, with its ctypes signature
 _u64, _u32, _i32, _vp, _cp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p
@@ -338,7 +339,9 @@ class Rambo:
 
     def query_seqs_ids(self, seqs, offsets, ids_cap: int, scratch=None, stream=None, check=True):
         """Returns (ids int32 tensor, id_offsets int64 tensor); raises
-        RamboError(ETRUNC) with .required set if ids_cap is too small."""
+        RamboError(ETRUNC) with .required set if ids_cap is too small. The
+        call's status (OK, or OK_EMPTYQ if some read held no valid window) is
+        left in self.last_status."""
         import torch
         n = offsets.numel() - 1
         if check:
@@ -355,7 +358,7 @@ class Rambo:
             e = RamboError(st, lib().rambo_last_error().decode())
             e.required = int(id_off[-1].item())
             raise e
-        _check(st)
+        self.last_status = _check(st)
         return ids[: int(id_off[-1].item())], id_off
 
     # -- options
@@ -372,8 +375,10 @@ class Rambo:
         ptr = None if counter is None else _dptr(counter, "counter", _i64())
         _check(lib().rambo_set_probe_counter(self._h, ptr))
 
-    def sync(self, stream=None) -> None:
-        _check(lib().rambo_sync(self._h, _stream(stream)))
+    def sync(self, stream=None) -> int:
+        """Wait for the handle's work on the stream; returns OK, or OK_EMPTYQ if
+        a query without a term ran since the last sync (raises on errors)."""
+        return _check(lib().rambo_sync(self._h, _stream(stream)))
 
     def autotune(self, seqs, offsets, out, stream=None) -> Tune:
         import torch

@@ -56,6 +56,7 @@ def test_invalid_create_reports_einval_without_touching_a_device(so):
     assert not L.rambo_create(100, 10, 9, 1 << 20, 2, 1)      # R > 8
     assert not L.rambo_create(100, 9000, 3, 1 << 20, 2, 1)    # B > 8192
     assert not L.rambo_create(100, 10, 3, 1 << 20, 0, 1)      # eta = 0
+    assert not L.rambo_create(100, 10, 3, 1 << 20, 17, 1)     # eta > 16
     L.rambo_destroy(None)                                     # NULL-safe
 
 

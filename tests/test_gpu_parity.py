@@ -384,3 +384,47 @@ def test_one_repetition_two_word_rows_one_hash():
                     got = to_host_u64(idx.query_seqs(seqs, offs))
                     assert np.array_equal(got, want), (mode, ee, sched, tile)
     idx.close()
+
+
+def test_empty_query_status():
+    """A read with no valid window answers every document and is reported
+    (RAMBO_OK_EMPTYQ): by rambo_sync after bitset queries, in both forms,
+    every schedule and tile (reads over several tiles included), and by the
+    id-list call itself; a batch whose reads all hold a term reports
+    RAMBO_OK, also when a read's only valid windows are not scout windows."""
+    idx, o, dm, reads, want = setup_case("rw4")
+    d5 = dm.doc(5)
+    termless = [b"", b"ACGT" * 7 + b"AC", b"N" * 200, b"ACGTX" * 40, (d5[:30] + b"N") * 100]
+    withterm = [d5[100:131], d5[:10_000], d5[5000:5100],
+                b"N" + d5[200:231] + b"N",                    # one valid window, not a scout window
+                b"N" * 2000 + d5[300:331] + b"N"]             # the same, in the 32nd tile of 64 windows
+    for s in withterm:
+        assert _ref.seq_terms(s).size > 0
+    everyone = _ref.ids_to_bits(range(idx.K), idx.K)
+    batches = {"termless": termless, "withterm": withterm, "mixed": withterm[:2] + termless[2:4] + withterm[2:]}
+    expect = {"termless": rb.OK_EMPTYQ, "withterm": rb.OK, "mixed": rb.OK_EMPTYQ}
+    dev = {}
+    for k, v in batches.items():
+        s, off = make_reads(v)
+        dev[k] = (to_dev(s), to_dev(off), np.stack([o.query_seq(x) for x in v]))
+    for x in termless:
+        assert np.array_equal(o.query_seq(x), everyone)
+    idx.sync()
+    for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
+        idx.set_mode(mode)
+        for sched in (0, 1, 2):
+            for tile in (64, 1024):
+                idx.set_tune(rb.Tune(4, tile, 8, 4, 1, sched))
+                for k, (s, off, wantk) in dev.items():
+                    got = to_host_u64(idx.query_seqs(s, off))
+                    assert np.array_equal(got, wantk), (mode, sched, tile, k)
+                    assert idx.sync() == expect[k], (mode, sched, tile, k)
+                    ids, id_off = idx.query_seqs_ids(s, off, ids_cap=idx.K * 8)
+                    assert idx.last_status == expect[k], (mode, sched, tile, k, "ids")
+    # term sets: the empty set is a query without a term
+    t = np.array([5, 6, 7], dtype=np.uint64)
+    idx.query_term_sets(to_dev(t), to_dev(np.array([0, 3, 3], dtype=np.uint64)))
+    assert idx.sync() == rb.OK_EMPTYQ
+    idx.query_term_sets(to_dev(t), to_dev(np.array([0, 1, 3], dtype=np.uint64)))
+    assert idx.sync() == rb.OK
+    idx.set_mode(rb.MODE_PLAIN)

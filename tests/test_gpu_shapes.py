@@ -1,6 +1,6 @@
 """Index shapes away from the workloads': every B from a single cell to a
 two-row-word split and past 1,024 (rows of 1 to 64 words), R from 1 to 8,
-eta from 1 to 5 (the generic row loop above 3), m not a power of two (the
+eta from 1 to 16 (the generic row loop above 3), m not a power of two (the
 multiply-high range reduction), K not a multiple of 64 (result padding).
 Every shape: the whole index against the oracle's bits on sampled BFUs, and
 every read in both forms, every resolve strategy and schedule, with and
@@ -23,6 +23,8 @@ SHAPES = [
     (300, 129, 5, 300_007, 5),    # rows of 8 words, eta = 5
     (640, 300, 3, 1 << 19, 2),    # rows of 16 words (4 lanes per term)
     (900, 2048, 2, 400_009, 3),   # rows of 64 words (16 lanes per term)
+    (200, 50, 3, 150_001, 16),    # the largest eta
+    (96, 8192, 2, 1 << 18, 7),    # the largest B: rows of 256 words (64 lanes per term)
 ]
 
 
