@@ -284,6 +284,24 @@ int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64_t *offset
                          uint64_t *scratch, uint32_t *ids, uint64_t *id_offsets, uint64_t ids_cap,
                          void *stream);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc between calls): rambo_query_seqs_ids with
+ * the same arguments, results and statuses, making no allocation of any kind.
+ * The answer sizes and scan scratch that rambo_query_seqs_ids allocates per
+ * handle come instead from one fixed array of the library, of
+ * RAMBO_NOALLOC_MAX_READS + 1 + RAMBO_NOALLOC_MAX_READS / 1024 + 64 uint64
+ * words (about 8 MiB), held on each device the library runs on until the
+ * process ends. n may be at most RAMBO_NOALLOC_MAX_READS (RAMBO_EINVAL
+ * beyond). Always the plain form (one wavefront per read), whatever
+ * rambo_set_mode chose. Synchronous on `stream`. Every call on one device
+ * shares that device's array, which keeps the last call's contents: calls
+ * from threads of this process are serialised by the library; calls that
+ * overlapped on one GPU would race. */
+#define RAMBO_NOALLOC_MAX_READS (1u << 20)
+int rambo_query_seqs_ids_noalloc(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
+                                 uint64_t *bits, uint32_t *ids, uint64_t *id_offsets, uint64_t ids_cap,
+                                 void *stream);
+
 /* Select the execution form of rambo_query_seqs (RAMBO_MODE_*). */
 int rambo_set_mode(rambo_t *h, int mode);
 

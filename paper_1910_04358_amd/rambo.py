@@ -63,6 +63,7 @@ SIGNATURES = {
     "rambo_query_kmers": ([_vp, _vp, _u64, _vp, _vp], _i32),
     "rambo_query_seqs": ([_vp, _vp, _vp, _u64, _vp, _vp], _i32),
     "rambo_query_seqs_ids": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp], _i32),
+    "rambo_query_seqs_ids_noalloc": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp], _i32),
     "rambo_set_mode": ([_vp, _i32], _i32),
     "rambo_set_resolve": ([_vp, _i32], _i32),
     "rambo_set_early_exit": ([_vp, _i32], _i32),
