@@ -31,11 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
-# Bytes one isolated random row read moves from HBM on this GPU: a read
-# request from L2 to memory carries a 128-byte line (a copy of 1 GiB issues
-# exactly 1 GiB / 128 B read requests; each probe of the query kernel issues
-# one request), see profiles/batched_query_K10000_traffic.md.
+# Bytes one isolated random row read moves from HBM on this GPU: every read
+# request from L2 to memory is a 128-byte request, for random 16-byte rows as
+# for streaming copies (request-size counters TCC_EA0_RDREQ_32B/64B/128B, one
+# 128-byte request per probe; profiles/probe_granule_MI355X.md).
 GRANULE = 128
+GRANULE_SOURCE = "profiles/probe_granule_MI355X.md"
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batched_query_K10000_traffic.json")
 
 
@@ -475,7 +476,8 @@ def main():
                      "useful_bytes_frac": (issued * row_bytes + io_bytes) / (batched_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "kernel": "batched query pass (k_batch_scout, k_batch_prep, scan, k_batch_main)",
                      "kernel_ms": batched_ms, "main_kernel_ms": kern_ms, "probes_per_launch": issued,
-                     "bytes_per_probe": max(GRANULE, row_bytes), "io_bytes": io_bytes,
+                     "bytes_per_probe": max(GRANULE, row_bytes), "bytes_per_probe_source": GRANULE_SOURCE,
+                     "io_bytes": io_bytes,
                      "random_read_ceiling": ceiling,
                      "frac_of_ceiling": (issued / (batched_ms * 1e-3) / ceiling["probes_per_s"]) if ceiling else None},
         "cpu_baseline": cpu,

@@ -45,6 +45,7 @@ def copy(nbytes: int = 1 << 30) -> float:
 
 
 def run(sizes_gib, rows, iters=16, reps=3, atomics=True, coop_rows=(32, 64, 128, 256)):
+    """Every case on buffers of each size; one JSON line per case."""
     import torch
     L = lib()
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
@@ -82,9 +83,16 @@ def main():
     ap.add_argument("--rows", default="4,16,64,128")
     ap.add_argument("--coop-rows", default="32,64,128,256")
     ap.add_argument("--iters", type=int, default=16)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--no-atomics", action="store_true", help="leave out the atomic OR case")
+    ap.add_argument("--copy-gib", type=float, default=0,
+                    help="also run the plain copy kernel over this many GiB (scale for byte counters)")
     a = ap.parse_args()
-    run([float(s) for s in a.sizes_gib.split(",")], [int(r) for r in a.rows.split(",")], iters=a.iters,
-        coop_rows=[int(r) for r in a.coop_rows.split(",") if r])
+    if a.copy_gib:
+        nbytes = int(a.copy_gib * (1 << 30)) // 16 * 16
+        print(json.dumps({"kind": "copy", "bytes": nbytes, "ms": copy(nbytes)}), flush=True)
+    run([float(s) for s in a.sizes_gib.split(",") if s], [int(r) for r in a.rows.split(",") if r], iters=a.iters,
+        reps=a.reps, atomics=not a.no_atomics, coop_rows=[int(r) for r in a.coop_rows.split(",") if r])
 
 
 if __name__ == "__main__":
