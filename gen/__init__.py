@@ -278,7 +278,7 @@ class TermWorkload:
 
 
 def term_workload(name: str) -> TermWorkload:
-    """The paper's two web-document index shapes (Section 6, document
+    """The paper's two web-document index shapes (Section 5.4, document
     indexing) on synthetic term sets: Wiki-dump-like (17,618 documents of
     ~650 terms, B=1,000, R=2, 200,000-bit BFUs) and ClueWeb09-like (50,000
     documents of ~450 terms, B=5,000, R=3, 20,000-bit BFUs); eta = 2."""

@@ -100,7 +100,7 @@ enum {
 /* ---------------------------------------------------------------------- */
 
 /* Allocate an empty index of K documents (ids 0..K-1; K is the capacity, so
- * documents can be added later, Section 3.2 "conducive to updates"), R
+ * documents can be added later: insertion into a built index, Section 3.2), R
  * repetitions of B BFUs of m bits each, eta Bloom hash functions, on the
  * current HIP device. The index is a bit-sliced array rows[R][m] of B-bit
  * rows, each padded to a power of two >= 32 bits, zeroed. Returns NULL on
@@ -113,7 +113,7 @@ enum { RAMBO_TERMS_OPAQUE = 1 };
 
 /* As rambo_create, with flags. RAMBO_TERMS_OPAQUE: an index of documents
  * given as sets of opaque 64-bit terms (word ids; the document indexing of
- * Section 6) instead of 31-mers: rambo_insert, rambo_insert_batch,
+ * Section 5.4) instead of 31-mers: rambo_insert, rambo_insert_batch,
  * rambo_query_kmers and rambo_query_term_sets take the values as they are
  * (no k-mer encoding, no range check: every 64-bit value is a term), and the
  * sequence entry points (rambo_insert_seqs, rambo_query_seqs,

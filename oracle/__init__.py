@@ -60,6 +60,8 @@ def lib():
             "orc_bfu_test_seq": ([vp, u32, vp, vp, u64], i32),
             "orc_popcount_bfu": ([vp, u32, u32], u64),
             "orc_bfu_test_seqs": ([vp, u32, vp, vp, vp, u64, vp, i32], None),
+            "orc_build_rep": ([vp, u32, vp, vp, u64, u64, u64, i32], i32),
+            "orc_alg2_rep": ([vp, u32, vp, vp, vp, u64, vp, i32, i32], None),
             "orc_query_kmer_def": ([vp, u64, vp], None),
             "orc_query_kmer_alg2": ([vp, u64, vp], None),
             "orc_query_seq_def": ([vp, vp, u64, vp], None),
@@ -230,6 +232,31 @@ class Oracle:
         out = np.zeros(n, dtype=np.uint8)
         lib().orc_bfu_test_seqs(self._h, r, _p(f), _p(seqs), _p(offsets), n, _p(out), nthreads or _nthreads())
         return out.astype(bool)
+
+    # -- one repetition at a time (indexes too large for host memory)
+    def new_rep(self) -> np.ndarray:
+        """Zeroed filters of one repetition, shape (B, wpb) uint64."""
+        return np.zeros((self.B, self.wpb), dtype=np.uint64)
+
+    def build_rep(self, r: int, rep_bits: np.ndarray, docs: np.ndarray, doc_len: int, d0: int, nd: int,
+                  nthreads=None) -> None:
+        """Algorithm 1 for repetition r only: documents d0..d0+nd-1 into rep_bits."""
+        assert rep_bits.shape == (self.B, self.wpb) and rep_bits.dtype == np.uint64 and rep_bits.flags.c_contiguous
+        docs = np.ascontiguousarray(docs, dtype=np.uint8)
+        assert docs.size >= nd * doc_len
+        if lib().orc_build_rep(self._h, r, _p(rep_bits), _p(docs), doc_len, d0, nd, nthreads or _nthreads()) != 0:
+            raise ValueError("repetition or document range out of range")
+
+    def alg2_rep(self, r: int, rep_bits: np.ndarray, seqs: np.ndarray, offsets: np.ndarray, out: np.ndarray,
+                 first: bool, nthreads=None) -> None:
+        """Repetition r of Algorithm 2 for every read, intersected into out (n, W)."""
+        assert rep_bits.shape == (self.B, self.wpb) and rep_bits.dtype == np.uint64
+        seqs = np.ascontiguousarray(seqs, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n = offsets.size - 1
+        assert out.shape == (n, self.W) and out.dtype == np.uint64 and out.flags.c_contiguous
+        lib().orc_alg2_rep(self._h, r, _p(rep_bits), _p(seqs), _p(offsets), n, _p(out), int(first),
+                           nthreads or _nthreads())
 
     # -- queries
     def query_kmer(self, x: int, mode=MODE_DEF) -> np.ndarray:

@@ -293,6 +293,66 @@ void orc_bfu_test_seqs(const orc_t *o, uint32_t r, const uint64_t *f, const uint
         out[i] = (uint8_t)orc_bfu_test_seq(o, r, f, seqs + offsets[i], offsets[i + 1] - offsets[i]);
 }
 
+static inline void setbit(uint64_t *out, uint64_t d) { out[d >> 6] |= 1ULL << (d & 63); }
+
+/* ---- one repetition at a time ---------------------------------------------
+ * The answer of Algorithm 2 is the intersection over repetitions of G_r (the
+ * documents of the BFUs of repetition r that hold every term), so an index
+ * too large for host memory can be evaluated one repetition at a time: the
+ * B filters of repetition r alone, rep_bits[B][wpb], built by Algorithm 1
+ * restricted to r, then G_r of every query intersected into its answer. */
+
+/* Algorithm 1 for repetition r only: the terms of documents d0 .. d0+nd-1
+ * (doc_len bytes each, concatenated in `docs`) into rep_bits[phi_r(d)].
+ * Threads own whole filters. */
+int orc_build_rep(const orc_t *o, uint32_t r, uint64_t *rep_bits, const uint8_t *docs, uint64_t doc_len,
+                  uint64_t d0, uint64_t nd, int nthreads) {
+    if (r >= o->R || d0 + nd > o->K) return -1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t b = 0; b < (int64_t)o->B; b++) {
+        uint64_t *f = rep_bits + (uint64_t)b * o->wpb;
+        for (uint64_t i = 0; i < nd; i++) {
+            if (orc_phi(o, r, d0 + i) != (uint32_t)b) continue;
+            const uint8_t *s = docs + i * doc_len;
+            for (uint64_t p = 0; p + KMER <= doc_len; p++) {
+                uint64_t x;
+                if (orc_window(s, p, &x)) bf_insert(o, r, f, x);
+            }
+        }
+    }
+    return 0;
+}
+
+/* Repetition r of Algorithm 2 for n sequence queries (seqs[offsets[i] ..
+ * offsets[i+1])): G_r = the union of the documents of every BFU of
+ * repetition r in which every term of the query passes (vacuously every BFU
+ * for a query without a term); out[i] (W words) becomes G_r if `first`, else
+ * out[i] AND G_r. Parallel over queries. */
+void orc_alg2_rep(const orc_t *o, uint32_t r, const uint64_t *rep_bits, const uint8_t *seqs,
+                  const uint64_t *offsets, uint64_t n, uint64_t *out, int first, int nthreads) {
+    const uint32_t *off = o->bucket_off + (size_t)r * (o->B + 1);
+    const uint64_t *cell_docs = o->bucket_doc + (size_t)r * o->K;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; i++) {
+        const uint8_t *s = seqs + offsets[i];
+        const uint64_t len = offsets[i + 1] - offsets[i];
+        uint64_t *G = calloc(o->W, 8);
+        for (uint32_t b = 0; b < o->B; b++) {
+            const uint64_t *f = rep_bits + (uint64_t)b * o->wpb;
+            int holds_all = 1;
+            for (uint64_t p = 0; p + KMER <= len && holds_all; p++) {
+                uint64_t x;
+                if (orc_window(s, p, &x) && !bf_test(o, r, f, x)) holds_all = 0;
+            }
+            if (holds_all)
+                for (uint32_t k = off[b]; k < off[b + 1]; k++) setbit(G, cell_docs[k]);
+        }
+        uint64_t *a = out + (uint64_t)i * o->W;
+        for (uint64_t w = 0; w < o->W; w++) a[w] = first ? G[w] : (a[w] & G[w]);
+        free(G);
+    }
+}
+
 uint64_t orc_popcount_bfu(const orc_t *o, uint32_t r, uint32_t b) {
     uint64_t c = 0;
     const uint64_t *f = bfu(o, r, b);
@@ -301,7 +361,6 @@ uint64_t orc_popcount_bfu(const orc_t *o, uint32_t r, uint32_t b) {
 }
 
 /* ---- queries ------------------------------------------------------------ */
-static inline void setbit(uint64_t *out, uint64_t d) { out[d >> 6] |= 1ULL << (d & 63); }
 
 /* Definition mode, one term: document d is reported iff for every repetition
  * r the BFU it belongs to, BFU(r, phi_r(d)), passes the Bloom test
@@ -317,36 +376,52 @@ void orc_query_kmer_def(const orc_t *o, uint64_t x, uint64_t *out) {
     }
 }
 
-/* Algorithm 2 taken literally for a term set Q (n terms): for each
- * repetition, test every BFU; G_r is the union of the document lists of
- * positive BFUs; the answer is the intersection of the G_r. "Q in BFU" holds
- * iff every term passes. With early_exit, a BFU test stops at its first
- * failing term and the repetitions stop once the running intersection is
- * empty (Section 3.3.1: the first FALSE is conclusive). Returns the number of
- * single-term Bloom tests performed. */
+/* The query of Section 3.3 / Algorithm 2 through the cells, for a term set Q
+ * of n terms. A cell b of repetition r is positive when its BFU holds every
+ * term of Q (its Bloom test passes for each). Within a repetition the
+ * documents of the positive cells are merged (a union: each document lies in
+ * exactly one cell), and across repetitions only documents found in every
+ * repetition remain (an intersection). Without terms every cell is
+ * positive. With early_exit a cell's test stops at the first term it does
+ * not hold, and no further repetition is examined once the remaining set is
+ * empty: an intersection with an empty set stays empty (Section 3.3.1).
+ * Returns the number of single-term Bloom tests performed. */
 static uint64_t alg2(const orc_t *o, const uint64_t *Q, uint64_t n, uint64_t *out, int early_exit) {
     uint64_t tests = 0;
-    uint64_t *G = malloc(o->W * 8);
+    uint8_t *positive = malloc(o->B);
+    uint64_t *merged = malloc(o->W * 8);
+    /* the remaining set starts as every document (bits >= K stay zero) */
     for (uint64_t w = 0; w < o->W; w++) out[w] = ~0ULL;
     if (o->K & 63) out[o->W - 1] = (1ULL << (o->K & 63)) - 1;
     for (uint32_t r = 0; r < o->R; r++) {
-        memset(G, 0, o->W * 8);
-        const uint32_t *off = o->bucket_off + (size_t)r * (o->B + 1);
         for (uint32_t b = 0; b < o->B; b++) {
             const uint64_t *f = bfu(o, r, b);
-            int in = 1;
+            positive[b] = 1;
             for (uint64_t i = 0; i < n; i++) {
                 tests++;
-                if (!bf_test(o, r, f, Q[i])) { in = 0; if (early_exit) break; }
+                if (!bf_test(o, r, f, Q[i])) {
+                    positive[b] = 0;
+                    if (early_exit) break;
+                }
             }
-            if (in)
-                for (uint32_t k = off[b]; k < off[b + 1]; k++) setbit(G, o->bucket_doc[(size_t)r * o->K + k]);
         }
-        uint64_t any = 0;
-        for (uint64_t w = 0; w < o->W; w++) { out[w] &= G[w]; any |= out[w]; }
-        if (early_exit && !any) break;
+        /* union of the documents of the positive cells */
+        memset(merged, 0, o->W * 8);
+        const uint32_t *off = o->bucket_off + (size_t)r * (o->B + 1);
+        const uint64_t *cell_docs = o->bucket_doc + (size_t)r * o->K;
+        for (uint32_t b = 0; b < o->B; b++)
+            if (positive[b])
+                for (uint32_t k = off[b]; k < off[b + 1]; k++) setbit(merged, cell_docs[k]);
+        /* intersection with what the earlier repetitions left */
+        uint64_t left = 0;
+        for (uint64_t w = 0; w < o->W; w++) {
+            out[w] &= merged[w];
+            left |= out[w];
+        }
+        if (early_exit && !left) break;
     }
-    free(G);
+    free(merged);
+    free(positive);
     return tests;
 }
 
@@ -409,7 +484,7 @@ uint64_t orc_query_seqs(const orc_t *o, const uint8_t *seqs, const uint64_t *off
     return tests;
 }
 
-/* ---- opaque terms (document indexing with word terms, Section 6) --------- */
+/* ---- opaque terms (document indexing with word terms, Section 5.4) --------- */
 /* Documents as sets of opaque 64-bit terms (word ids): Algorithm 1 and the
  * queries of Section 3.3 with the terms taken as they are -- no k-mer
  * encoding, any 64-bit value is a term. */

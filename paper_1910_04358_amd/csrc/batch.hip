@@ -3,8 +3,9 @@
 // items of the reads still alive, replayed from captured HIP graphs, with a
 // launch shape chosen by an autotuner.
 //
-// Most reads end on their scout windows (Section 3.3.1: the first FALSE is
-// conclusive); the scout pass answers them and leaves them out of the queue.
+// Most reads end on their scout windows (Section 3.3.1: once a term has
+// emptied the running intersection, no later term can bring a document
+// back); the scout pass answers them and leaves them out of the queue.
 // The queue runs longest work first (see the order below). A read that fits
 // one tile is finished by the wave that took it, from its LDS masks. Longer
 // reads are spread over many waves; their tiles AND into a per-read mask in

@@ -1,5 +1,5 @@
 """Opaque-term indexes (documents as sets of word ids, the document indexing
-setting of Section 6) and term-set queries, through the C ABI, bit-exact
+setting of Section 5.4) and term-set queries, through the C ABI, bit-exact
 against the oracle's term functions on the same generated inputs: the whole
 index, single terms under every resolve strategy, term sets with and without
 early exit, rows of 1 to 256 words, k-mer term sets on a k-mer index, and the

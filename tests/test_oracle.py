@@ -364,7 +364,7 @@ def test_fold_equals_rebuild_with_half_the_cells():
 
 
 # ---------------------------------------------------------------- word terms
-# Document indexing with opaque word terms (Section 6): the same method with
+# Document indexing with opaque word terms (Section 5.4): the same method with
 # the terms taken as they are.
 def _term_index(K, B, R, m, eta=2, seed=77, mean=40, vocab=2000, dseed=1201):
     dm = gen.TermDocModel(seed=dseed, n_docs=K, mean_terms=mean, vocab=vocab)
@@ -463,3 +463,157 @@ def test_terms_false_positive_law():
     p = (fill ** eta).mean()
     lemma = q.size * K * p ** R
     assert abs(observed - lemma) < 0.2 * lemma, (observed, lemma)
+
+
+def test_lemma_4_1_across_multiplicities():
+    """Lemma 4.1 for any multiplicity V (the curve of Figure 4): a term held
+    by V documents is reported for a document that does not hold it with
+    probability (1 - (1 - p)(1 - 1/B)^V)^R -- in each repetition the
+    document's cell holds one of the V holders, or its Bloom filter errs.
+    Documents shaped like the K=1,000 workload (mutant families of one
+    ancestor with 1 % substitutions; B=32, R=4, eta=3), in families of 5, 20
+    and 50 so that present terms are held by 1 to 50 documents, shorter and
+    with a smaller m so that false positives are frequent enough to count at
+    V = 1. Present terms are bucketed by their exact V (brute force); per
+    bucket the observed count must match the sharp prediction with the
+    realised cells and fills, and the lemma with the mean p."""
+    B, R, eta, L, m = 32, 4, 3, 2000, 1 << 18
+    families = [gen.DocModel(seed=1402 + k, n_docs=500, length=L, docs_per_anc=fam, mu_lo=0.01, mu_hi=0.01)
+                for k, fam in enumerate((5, 20, 50))]
+    K = 500 * len(families)
+    o = oracle.Oracle(K, B, R, m, eta, 2402)
+    docs = np.concatenate([dm.docs(0, 500) for dm in families])
+    o.build_docs(docs, L, 0, K)
+    table = _ref.KmerTable({d: _ref.seq_terms(docs[d * L:(d + 1) * L].tobytes()) for d in range(K)})
+    q = np.concatenate([gen.kmer_queries(dm, 3402 + k, 4000, 1.0)[0] for k, dm in enumerate(families)])
+    cq = _ref.canon_np(q)
+    res = o.query_kmers(cq)
+    phis = o.phis()
+    fill = np.array([[o.bfu_popcount(r, b) / m for b in range(B)] for r in range(R)])
+    fe = fill ** eta                                   # per-BFU false-positive rate of an absent term
+    p = fe.mean()
+    bits = np.unpackbits(res.view(np.uint8), axis=1, bitorder="little")[:, :K].astype(bool)
+    buckets = [(1, 1), (2, 5), (6, 24), (25, 50)]
+    stats = {bk: [0.0, 0.0, 0.0] for bk in buckets}    # observed, sharp prediction, lemma
+    for i in range(q.size):
+        holders = table.docs_with(int(cq[i]))
+        V = holders.size
+        bk = next((b for b in buckets if b[0] <= V <= b[1]), None)
+        if bk is None:
+            continue
+        assert bits[i, holders].all()                  # no false negative
+        non = np.ones(K, dtype=bool)
+        non[holders] = False
+        pr = np.ones(K)
+        for r in range(R):
+            hc = np.zeros(B, dtype=bool)
+            hc[phis[r, holders]] = True
+            pr *= np.where(hc[phis[r]], 1.0, fe[r, phis[r]])
+        st = stats[bk]
+        st[0] += bits[i, non].sum()
+        st[1] += pr[non].sum()
+        st[2] += (K - V) * (1 - (1 - p) * (1 - 1 / B) ** V) ** R
+    for bk, (obs, sharp, lemma) in stats.items():
+        assert sharp > 50, (bk, sharp)
+        assert abs(obs - sharp) < max(8 * math.sqrt(sharp), 0.05 * sharp), (bk, obs, sharp)
+        assert abs(obs - lemma) < 0.15 * lemma, (bk, obs, lemma)
+
+
+# ------------------------------------------- sampled BFUs and one repetition
+def _reads_with_edges(dm, rm, n):
+    reads = gen.reads(dm, rm, n)
+    extra = [b"", b"N" * 50, b"ACGT" * 7, dm.doc(3, 10, 31), dm.doc(5, 0, 200).lower()]
+    seqs = [reads.read(i) for i in range(reads.n)] + extra
+    offs = np.zeros(len(seqs) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(s) for s in seqs])
+    return np.frombuffer(b"".join(seqs), dtype=np.uint8).copy(), offs
+
+
+def test_single_bfu_functions_reproduce_the_oracle():
+    """The functions that check sampled documents of indexes too large for
+    the oracle -- one BFU built from the documents of its cell, a read tested
+    against one filter of repetition r -- reproduce the whole oracle: the
+    filter built from cell (r, b)'s documents is BFU(r, b), and ANDing over r
+    the tests of document d's filters gives d's answer from the
+    per-document definition (Section 3.3.1), for every document and read
+    (reads without a term pass vacuously). A filter tested with another
+    repetition's hash functions gives other answers, so that slip would
+    fail here."""
+    K, B, R, m, eta, L = 40, 5, 3, 1 << 14, 2, 600
+    dm = gen.DocModel(seed=131, n_docs=K, length=L, docs_per_anc=4, mu_lo=0.02, mu_hi=0.02)
+    o = oracle.Oracle(K, B, R, m, eta, 55)
+    docs = dm.docs(0, K)
+    o.build_docs(docs, L, 0, K)
+    bits, phis = o.bits(), o.phis()
+    F = {}
+    for r in range(R):
+        for b in range(B):
+            f = o.new_bfu()
+            for d in np.nonzero(phis[r] == b)[0]:
+                o.bfu_insert_seq(r, f, docs[d * L:(d + 1) * L])
+            assert np.array_equal(f, bits[r, b]), (r, b)
+            F[(r, b)] = f
+    rm = gen.ReadModel(qseed=132, src_lo=0, src_hi=K, len_kind=1, lo=31, hi=200, err_lo=0.0, err_hi=0.02)
+    seqs, offs = _reads_with_edges(dm, rm, 300)
+    want, _ = o.query_seqs(seqs, offs, oracle.MODE_DEF)
+    wbits = np.unpackbits(want.view(np.uint8), axis=1, bitorder="little")[:, :K].astype(bool)
+    assert 10 < wbits.sum() < wbits.size
+    slip = False
+    for d in range(K):
+        keep = np.ones(offs.size - 1, dtype=bool)
+        for r in range(R):
+            t = o.bfu_test_seqs(r, F[(r, int(phis[r, d]))], seqs, offs)
+            keep &= t
+            other = o.bfu_test_seqs((r + 1) % R, F[(r, int(phis[r, d]))], seqs, offs)
+            slip |= not np.array_equal(other, t)
+        assert np.array_equal(keep, wbits[:, d]), d
+        for i in (0, offs.size - 2, offs.size - 4):
+            s = seqs[int(offs[i]):int(offs[i + 1])].tobytes()
+            one = all(o.bfu_test_seq(r, F[(r, int(phis[r, d]))], s) for r in range(R))
+            assert one == wbits[i, d]
+    assert slip
+    assert o.bfu_test_seq(0, o.new_bfu(), b"N" * 40)       # no term: vacuously in any filter
+    assert not o.bfu_test_seq(0, o.new_bfu(), dm.doc(1, 0, 31))
+
+
+def test_one_repetition_at_a_time_equals_the_whole_oracle():
+    """Algorithm 1 restricted to one repetition, over documents given in
+    chunks, fills exactly that repetition's filters; Algorithm 2 taken one
+    repetition at a time (each repetition's union of positive cells,
+    intersected into the answer) gives the whole oracle's answers in both
+    modes, including reads without a term; with m far above the number of
+    terms it gives RAMBO over exact sets (brute force)."""
+    for (K, B, R, m, eta, L) in ((60, 7, 3, 1 << 13, 2, 500), (50, 4, 2, 1 << 24, 3, 300)):
+        dm = gen.DocModel(seed=K + B, n_docs=K, length=L, docs_per_anc=5, mu_lo=0.02, mu_hi=0.02)
+        o = oracle.Oracle(K, B, R, m, eta, 71)
+        docs = dm.docs(0, K)
+        o.build_docs(docs, L, 0, K)
+        rm = gen.ReadModel(qseed=K, src_lo=0, src_hi=K, len_kind=1, lo=31, hi=150, err_lo=0.0, err_hi=0.02)
+        seqs, offs = _reads_with_edges(dm, rm, 400)
+        n = offs.size - 1
+        out = np.zeros((n, o.W), dtype=np.uint64)
+        bits = o.bits()
+        for r in range(R):
+            rep = o.new_rep()
+            for c0 in range(0, K, 17):                    # documents in chunks
+                c1 = min(K, c0 + 17)
+                o.build_rep(r, rep, docs[c0 * L:c1 * L], L, c0, c1 - c0)
+            assert np.array_equal(rep, bits[r]), r
+            o.alg2_rep(r, rep, seqs, offs, out, first=(r == 0))
+        want_def, _ = o.query_seqs(seqs, offs, oracle.MODE_DEF)
+        want_alg2, _ = o.query_seqs(seqs, offs, oracle.MODE_ALG2, early_exit=True)
+        assert np.array_equal(out, want_def)
+        assert np.array_equal(out, want_alg2)
+        everyone = _ref.ids_to_bits(range(K), K)
+        assert np.array_equal(out[n - 4], everyone) and np.array_equal(out[n - 5], everyone)
+        if m >= 1 << 20:
+            table = _ref.KmerTable({d: _ref.seq_terms(docs[d * L:(d + 1) * L].tobytes()) for d in range(K)})
+            phis = o.phis()
+            cell = {(r, b): set().union(*[table.sets[d] for d in range(K) if phis[r, d] == b])
+                    for r in range(R) for b in range(B)}
+            for i in range(n):
+                Q = set(_ref.seq_terms(seqs[int(offs[i]):int(offs[i + 1])].tobytes()).tolist())
+                ex = {e for e in range(K) if all(Q <= cell[(r, phis[r, e])] for r in range(R))}
+                assert _ref.bits_to_ids(out[i], K) == ex, i
+    with pytest.raises(ValueError):
+        o.build_rep(R, o.new_rep(), docs, L, 0, 1)
