@@ -109,7 +109,11 @@ enum {
  * its device memory. */
 rambo_t *rambo_create(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed);
 
-enum { RAMBO_TERMS_OPAQUE = 1 };
+enum {
+    RAMBO_TERMS_OPAQUE = 1, /* creation flag: documents are sets of opaque terms */
+    RAMBO_SHARD = 2,        /* reported by rambo_layout (and kept in index
+                               files) for an index made by rambo_create_shard */
+};
 
 /* As rambo_create, with flags. RAMBO_TERMS_OPAQUE: an index of documents
  * given as sets of opaque 64-bit terms (word ids; the document indexing of
@@ -195,6 +199,48 @@ int rambo_copy_rows(rambo_t *h, uint64_t offset, uint64_t bytes, void *dst);
  * out of range, RAMBO_ENOMEM if the device cannot hold the index. */
 int rambo_save(rambo_t *h, const char *path);
 rambo_t *rambo_load(const char *path);
+
+/* ---------------------------------------------------------------------- */
+/* Sharding by document (Section 5.3, Figure 3)                            */
+/* ---------------------------------------------------------------------- */
+
+/* Routing: shard[i] = tau(doc_ids[i]) = ((a d + b) mod P) mod G, with P =
+ * 2^61 - 1, a = 1 + x0 mod (P - 1), b = x1 mod P for the first two outputs
+ * x0, x1 of SplitMix64 seeded with route_seed -- a random (2-universal for
+ * ids below P) hash of the document id picking one of G shards. Device
+ * arrays (n ids, n outputs); enqueued on `stream`. RAMBO_EINVAL if G = 0. */
+int rambo_route(const uint64_t *doc_ids, uint64_t n, uint32_t G, uint64_t route_seed, uint32_t *shard,
+                void *stream);
+
+/* A shard: an index of K local documents (local ids 0..K-1) where local
+ * document l stands for global document global_ids[l] (host array of K
+ * ids, copied). Everything is as rambo_create with (K, B, R, m, eta, seed)
+ * except the cells: local document l lies in cell phi_r(global_ids[l]) of
+ * repetition r, the node-local partition of the global id. G shards made
+ * with the same (B, R, m, eta, seed) over the documents routed to them
+ * (rambo_route) are, stacked, the index built directly with the two-level
+ * partition B * tau(d) + phi_r(d) over G * B cells: a document's answer is
+ * its answer in its own shard, which answers with a K-bit row over its
+ * local ids (rambo_stack_slice puts it back at the global ids). Inserts and
+ * queries take local ids. rambo_save keeps the ids (RAMBO_SHARD in the file
+ * header, the K ids after it) and rambo_load restores them. Errors as
+ * rambo_create; RAMBO_EINVAL for a null global_ids. */
+rambo_t *rambo_create_shard(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed,
+                            const uint64_t *global_ids);
+
+/* The global ids of a shard's local documents (host array of K words). */
+int rambo_shard_ids(const rambo_t *h, uint64_t *out);
+
+/* Stacking: for every query i < n and every local document l set in
+ * slice[i * W + (l >> 6)] (the shard's answer rows, device, W =
+ * rambo_result_words of the shard), set bit global_ids[l] of row i of out
+ * (device, n rows of out_words words). ORs into out, which the caller zeroes
+ * before stacking the first shard; the shards of one partition own disjoint
+ * documents, so any order of shards gives the same rows. Enqueued on
+ * `stream`. RAMBO_EINVAL if h is not a shard or a global id does not fit
+ * out_words. */
+int rambo_stack_slice(rambo_t *h, const uint64_t *slice, uint64_t n, uint64_t *out, uint64_t out_words,
+                      void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Construction (Algorithm 1)                                              */

@@ -43,6 +43,9 @@ def lib():
         u64, u32, i32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
         sig = {
             "orc_new": ([u64, u32, u32, u64, u32, u64, i32], vp),
+            "orc_new_cells": ([u64, u32, u32, u64, u32, u64, vp, i32], vp),
+            "orc_route": ([u64, u32, u64], u32),
+            "orc_cells": ([vp, vp], None),
             "orc_free": ([vp], None),
             "orc_bits": ([vp], vp),
             "orc_wpb": ([vp], u64),
@@ -109,12 +112,25 @@ def window(seq: bytes, p: int = 0):
     return int(out.value) if ok else None
 
 
-class Oracle:
-    """A RAMBO index on the CPU: R x B Bloom filters of m bits (BFU-major)."""
+def route(route_seed: int, G: int, ids) -> np.ndarray:
+    """tau(d) for each document id: the shard of Section 5.3's routing."""
+    return np.array([lib().orc_route(route_seed, G, int(d)) for d in ids], dtype=np.int64)
 
-    def __init__(self, K, B, R, m, eta, seed, alloc_bits=True, _handle=None):
+
+class Oracle:
+    """A RAMBO index on the CPU: R x B Bloom filters of m bits (BFU-major).
+    With `cells` (an (R, K) table of cells < B), the partition is that table
+    instead of phi_r (the two-level partition of Section 5.3)."""
+
+    def __init__(self, K, B, R, m, eta, seed, alloc_bits=True, _handle=None, cells=None):
         self.K, self.B, self.R, self.m, self.eta, self.seed = K, B, R, m, eta, seed
         L = lib()
+        if _handle is None and cells is not None:
+            c = np.ascontiguousarray(cells, dtype=np.uint32)
+            assert c.shape == (R, K)
+            _handle = L.orc_new_cells(K, B, R, m, eta, seed, _p(c), int(alloc_bits))
+            if not _handle:
+                raise ValueError("cell table out of range")
         self._h = _handle if _handle is not None else L.orc_new(K, B, R, m, eta, seed, int(alloc_bits))
         if not self._h:
             raise MemoryError("oracle allocation failed")
@@ -133,7 +149,15 @@ class Oracle:
         return int(lib().orc_phi(self._h, r, d))
 
     def phis(self) -> np.ndarray:
+        """phi_r(d) for every r and d: the partition hash (see cells())."""
         return np.array([[self.phi(r, d) for d in range(self.K)] for r in range(self.R)], dtype=np.int64)
+
+    def cells(self) -> np.ndarray:
+        """The cell of every document in every repetition, shape (R, K): phi_r,
+        or the explicit table the index was created with."""
+        out = np.zeros((self.R, self.K), dtype=np.uint32)
+        lib().orc_cells(self._h, _p(out))
+        return out.astype(np.int64)
 
     def h(self, r: int, j: int, x: int) -> int:
         return int(lib().orc_h(self._h, r, j, x))

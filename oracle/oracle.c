@@ -60,6 +60,7 @@ typedef struct {
     uint64_t *pa, *pb;                 /* [R] */
     uint64_t *Alo, *Ahi, *Clo, *Chi;   /* [R * eta] */
     uint64_t *bits;                    /* [R][B][wpb], may be NULL */
+    uint32_t *cells;                   /* [R][K] explicit partition, or NULL: phi_r */
     uint32_t *bucket_off;              /* [R][B + 1] */
     uint64_t *bucket_doc;              /* [R][K] documents grouped by cell, ascending */
 } orc_t;
@@ -76,6 +77,23 @@ static uint64_t sm_next(uint64_t *s) {
 uint32_t orc_phi(const orc_t *o, uint32_t r, uint64_t d) {
     u128 v = (u128)o->pa[r] * d + o->pb[r];
     return (uint32_t)((uint64_t)(v % P61) % o->B);
+}
+
+/* The cell of document d in repetition r: phi_r(d), or, for an index whose
+ * partition is given as a table (the two-level partition of Section 5.3),
+ * the table's entry. */
+static uint32_t cell_of(const orc_t *o, uint32_t r, uint64_t d) {
+    return o->cells ? o->cells[(size_t)r * o->K + d] : orc_phi(o, r, d);
+}
+
+/* Routing of Section 5.3: tau(d) = ((a d + b) mod P) mod G, a random hash of
+ * the document id that picks one of G shards, with a = 1 + x0 mod (P - 1),
+ * b = x1 mod P for the first two SplitMix64 outputs x0, x1 of route_seed. */
+uint32_t orc_route(uint64_t route_seed, uint32_t G, uint64_t d) {
+    uint64_t s = route_seed;
+    const uint64_t a = 1 + sm_next(&s) % (P61 - 1), b = sm_next(&s) % P61;
+    u128 v = (u128)a * d + b;
+    return (uint32_t)((uint64_t)(v % P61) % G);
 }
 
 /* ---- Bloom filter hash h_{r,j} (Section 2.1) ---------------------------- */
@@ -133,21 +151,27 @@ static void build_buckets(orc_t *o) {
     o->bucket_doc = malloc((size_t)o->R * o->K * sizeof(uint64_t));
     for (uint32_t r = 0; r < o->R; r++) {
         uint32_t *off = o->bucket_off + (size_t)r * (o->B + 1);
-        for (uint64_t d = 0; d < o->K; d++) off[orc_phi(o, r, d) + 1]++;
+        for (uint64_t d = 0; d < o->K; d++) off[cell_of(o, r, d) + 1]++;
         for (uint32_t b = 0; b < o->B; b++) off[b + 1] += off[b];
         uint32_t *fill = calloc(o->B, sizeof(uint32_t));
         for (uint64_t d = 0; d < o->K; d++) {
-            uint32_t b = orc_phi(o, r, d);
+            uint32_t b = cell_of(o, r, d);
             o->bucket_doc[(size_t)r * o->K + off[b] + fill[b]++] = d;
         }
         free(fill);
     }
 }
 
-orc_t *orc_new(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed,
-               int alloc_bits) {
+static orc_t *new_index(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed,
+                        int alloc_bits, const uint32_t *cells) {
     if (K == 0 || B == 0 || R == 0 || m == 0 || eta == 0 || K >= P61) return NULL;
     orc_t *o = calloc(1, sizeof(orc_t));
+    if (cells) {
+        for (uint64_t i = 0; i < (uint64_t)R * K; i++)
+            if (cells[i] >= B) { free(o); return NULL; }
+        o->cells = malloc((size_t)R * K * sizeof(uint32_t));
+        memcpy(o->cells, cells, (size_t)R * K * sizeof(uint32_t));
+    }
     o->K = K; o->B = B; o->R = R; o->m = m; o->eta = eta; o->seed = seed;
     o->wpb = (m + 63) / 64;
     o->W = (K + 63) / 64;
@@ -176,8 +200,23 @@ orc_t *orc_new(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uin
     return o;
 }
 
+orc_t *orc_new(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed, int alloc_bits) {
+    return new_index(K, B, R, m, eta, seed, alloc_bits, NULL);
+}
+
+/* An index whose partition is the table cells[r * K + d] (< B) instead of
+ * phi_r; the Bloom hash functions are those of orc_new with the same seed,
+ * R and eta (they do not depend on B). Used for the two-level partition
+ * b * tau(d) + phi_r(d) of Section 5.3 and for shards whose documents keep
+ * their global ids. NULL if a cell is out of range. */
+orc_t *orc_new_cells(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed,
+                     const uint32_t *cells, int alloc_bits) {
+    return new_index(K, B, R, m, eta, seed, alloc_bits, cells);
+}
+
 void orc_free(orc_t *o) {
     if (!o) return;
+    free(o->cells);
     free(o->pa); free(o->pb); free(o->Alo); free(o->Ahi); free(o->Clo); free(o->Chi);
     free(o->bits); free(o->bucket_off); free(o->bucket_doc);
     free(o);
@@ -222,7 +261,7 @@ int orc_insert_kmers(orc_t *o, uint64_t d, const uint64_t *kmers, uint64_t n) {
     for (uint64_t i = 0; i < n; i++)
         if (kmers[i] >> 62) return -1;
     for (uint32_t r = 0; r < o->R; r++) {
-        uint64_t *f = bfu(o, r, orc_phi(o, r, d));
+        uint64_t *f = bfu(o, r, cell_of(o, r, d));
         for (uint64_t i = 0; i < n; i++) bf_insert(o, r, f, orc_canon(kmers[i]));
     }
     return 0;
@@ -233,7 +272,7 @@ int orc_insert_kmers(orc_t *o, uint64_t d, const uint64_t *kmers, uint64_t n) {
 int orc_insert_seq(orc_t *o, uint64_t d, const uint8_t *seq, uint64_t len) {
     if (d >= o->K) return -1;
     for (uint32_t r = 0; r < o->R; r++) {
-        uint64_t *f = bfu(o, r, orc_phi(o, r, d));
+        uint64_t *f = bfu(o, r, cell_of(o, r, d));
         for (uint64_t p = 0; p + KMER <= len; p++) {
             uint64_t x;
             if (orc_window(seq, p, &x)) bf_insert(o, r, f, x);
@@ -254,7 +293,7 @@ int orc_build_docs(orc_t *o, const uint8_t *docs, uint64_t doc_len, uint64_t d0,
         uint32_t r = (uint32_t)(c / o->B), b = (uint32_t)(c % o->B);
         uint64_t *f = bfu(o, r, b);
         for (uint64_t i = 0; i < nd; i++) {
-            if (orc_phi(o, r, d0 + i) != b) continue;
+            if (cell_of(o, r, d0 + i) != b) continue;
             const uint8_t *s = docs + i * doc_len;
             for (uint64_t p = 0; p + KMER <= doc_len; p++) {
                 uint64_t x;
@@ -312,7 +351,7 @@ int orc_build_rep(const orc_t *o, uint32_t r, uint64_t *rep_bits, const uint8_t 
     for (int64_t b = 0; b < (int64_t)o->B; b++) {
         uint64_t *f = rep_bits + (uint64_t)b * o->wpb;
         for (uint64_t i = 0; i < nd; i++) {
-            if (orc_phi(o, r, d0 + i) != (uint32_t)b) continue;
+            if (cell_of(o, r, d0 + i) != (uint32_t)b) continue;
             const uint8_t *s = docs + i * doc_len;
             for (uint64_t p = 0; p + KMER <= doc_len; p++) {
                 uint64_t x;
@@ -371,7 +410,7 @@ void orc_query_kmer_def(const orc_t *o, uint64_t x, uint64_t *out) {
     memset(out, 0, o->W * 8);
     for (uint64_t d = 0; d < o->K; d++) {
         int keep = 1;
-        for (uint32_t r = 0; r < o->R && keep; r++) keep = bf_test(o, r, bfu(o, r, orc_phi(o, r, d)), x);
+        for (uint32_t r = 0; r < o->R && keep; r++) keep = bf_test(o, r, bfu(o, r, cell_of(o, r, d)), x);
         if (keep) setbit(out, d);
     }
 }
@@ -448,7 +487,7 @@ void orc_query_seq_def(const orc_t *o, const uint8_t *seq, uint64_t len, uint64_
         int keep = 1;
         for (uint64_t i = 0; i < n && keep; i++)
             for (uint32_t r = 0; r < o->R && keep; r++)
-                keep = bf_test(o, r, bfu(o, r, orc_phi(o, r, d)), Q[i]);
+                keep = bf_test(o, r, bfu(o, r, cell_of(o, r, d)), Q[i]);
         if (keep) setbit(out, d);
     }
     free(Q);
@@ -491,7 +530,7 @@ uint64_t orc_query_seqs(const orc_t *o, const uint8_t *seqs, const uint64_t *off
 int orc_insert_terms(orc_t *o, uint64_t d, const uint64_t *t, uint64_t n) {
     if (d >= o->K) return -1;
     for (uint32_t r = 0; r < o->R; r++) {
-        uint64_t *f = bfu(o, r, orc_phi(o, r, d));
+        uint64_t *f = bfu(o, r, cell_of(o, r, d));
         for (uint64_t i = 0; i < n; i++) bf_insert(o, r, f, t[i]);
     }
     return 0;
@@ -507,7 +546,7 @@ int orc_build_term_docs(orc_t *o, const uint64_t *t, const uint64_t *offs, uint6
         uint32_t r = (uint32_t)(c / o->B), b = (uint32_t)(c % o->B);
         uint64_t *f = bfu(o, r, b);
         for (uint64_t k = 0; k < nd; k++) {
-            if (orc_phi(o, r, d0 + k) != b) continue;
+            if (cell_of(o, r, d0 + k) != b) continue;
             for (uint64_t i = offs[k]; i < offs[k + 1]; i++) bf_insert(o, r, f, t[i]);
         }
     }
@@ -522,7 +561,7 @@ void orc_query_termset_def(const orc_t *o, const uint64_t *Q, uint64_t n, uint64
     for (uint64_t d = 0; d < o->K; d++) {
         int keep = 1;
         for (uint64_t i = 0; i < n && keep; i++)
-            for (uint32_t r = 0; r < o->R && keep; r++) keep = bf_test(o, r, bfu(o, r, orc_phi(o, r, d)), Q[i]);
+            for (uint32_t r = 0; r < o->R && keep; r++) keep = bf_test(o, r, bfu(o, r, cell_of(o, r, d)), Q[i]);
         if (keep) setbit(out, d);
     }
 }
@@ -562,6 +601,10 @@ orc_t *orc_fold(const orc_t *o) {
     if (o->B % 2 || !o->bits) return NULL;
     orc_t *f = orc_new(o->K, o->B, o->R, o->m, o->eta, o->seed, 0);
     f->B = o->B / 2;
+    if (o->cells) {  /* an explicit partition folds the same way: cell mod B/2 */
+        f->cells = malloc((size_t)f->R * f->K * sizeof(uint32_t));
+        for (uint64_t i = 0; i < (uint64_t)f->R * f->K; i++) f->cells[i] = o->cells[i] % f->B;
+    }
     f->bits = calloc((size_t)f->R * f->B * f->wpb, sizeof(uint64_t));
     for (uint32_t r = 0; r < o->R; r++)
         for (uint32_t b = 0; b < f->B; b++) {
@@ -575,16 +618,22 @@ orc_t *orc_fold(const orc_t *o) {
     f->bucket_doc = malloc((size_t)f->R * f->K * sizeof(uint64_t));
     for (uint32_t r = 0; r < f->R; r++) {
         uint32_t *off = f->bucket_off + (size_t)r * (f->B + 1);
-        for (uint64_t d = 0; d < f->K; d++) off[orc_phi(o, r, d) % f->B + 1]++;
+        for (uint64_t d = 0; d < f->K; d++) off[cell_of(o, r, d) % f->B + 1]++;
         for (uint32_t b = 0; b < f->B; b++) off[b + 1] += off[b];
         uint32_t *fill = calloc(f->B, sizeof(uint32_t));
         for (uint64_t d = 0; d < f->K; d++) {
-            uint32_t b = orc_phi(o, r, d) % f->B;
+            uint32_t b = cell_of(o, r, d) % f->B;
             f->bucket_doc[(size_t)r * f->K + off[b] + fill[b]++] = d;
         }
         free(fill);
     }
     return f;
+}
+
+/* the cell of every document in every repetition: out[r * K + d] */
+void orc_cells(const orc_t *o, uint32_t *out) {
+    for (uint32_t r = 0; r < o->R; r++)
+        for (uint64_t d = 0; d < o->K; d++) out[(size_t)r * o->K + d] = cell_of(o, r, d);
 }
 
 /* cell of document d in repetition r as this oracle's index sees it */

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librambo.so")
 MICRO = os.path.join(HERE, "libmicro.so")
 
-SOURCES = ["api.hip", "build.hip", "query.hip", "batch.hip", "scan.hip", "server.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "build.hip", "query.hip", "batch.hip", "scan.hip", "server.hip", "noalloc.hip", "shard.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RAMBO_OFFLOAD_ARCH", "gfx950")

@@ -53,11 +53,14 @@ static void derive_hashes(rambo_s *h) {
         h->Chi[i] = splitmix_next(s);
     }
     // phi_r(d) = ((a_r d + b_r) mod P) mod B, Carter-Wegman over the Mersenne
-    // prime P; a_r d + b_r < 2^122 fits 128 bits.
+    // prime P; a_r d + b_r < 2^125 fits 128 bits. A shard's local document d
+    // takes the cells of its global id (Section 5.3: the node-local partition
+    // of the global document).
     h->phi.resize((size_t)h->R * h->K);
     for (uint32_t r = 0; r < h->R; r++) {
         for (uint64_t d = 0; d < h->K; d++) {
-            unsigned __int128 v = (unsigned __int128)h->pa[r] * d + h->pb[r];
+            const uint64_t id = h->gids.empty() ? d : h->gids[d];
+            unsigned __int128 v = (unsigned __int128)h->pa[r] * id + h->pb[r];
             h->phi[(size_t)r * h->K + d] = (uint32_t)((uint64_t)(v % P61) % h->B);
         }
     }
@@ -72,6 +75,7 @@ static void free_device(rambo_s *h) {
     if (h->d_boff) (void)hipFree(h->d_boff);
     if (h->d_bdoc) (void)hipFree(h->d_bdoc);
     if (h->d_invalid) (void)hipFree(h->d_invalid);
+    if (h->d_gids) (void)hipFree(h->d_gids);
     if (h->aux) (void)hipStreamDestroy(h->aux);
     h->rows = nullptr;
 }
@@ -113,6 +117,10 @@ static int upload_tables(rambo_s *h) {
     HIP_CHECK(hipMemcpy(h->d_boff, boff.data(), boff.size() * 4, hipMemcpyHostToDevice));
     HIP_CHECK(hipMalloc(&h->d_bdoc, bdoc.size() * 4));
     HIP_CHECK(hipMemcpy(h->d_bdoc, bdoc.data(), bdoc.size() * 4, hipMemcpyHostToDevice));
+    if (!h->gids.empty() && !h->d_gids) {
+        HIP_CHECK(hipMalloc(&h->d_gids, h->gids.size() * 8));
+        HIP_CHECK(hipMemcpy(h->d_gids, h->gids.data(), h->gids.size() * 8, hipMemcpyHostToDevice));
+    }
     return RAMBO_OK;
 }
 
@@ -133,6 +141,11 @@ RAMBO_API rambo_t *rambo_create_ex(uint64_t K, uint32_t B, uint32_t R, uint64_t 
         fail(RAMBO_EINVAL, "rambo_create_ex: unknown flags 0x%x", flags);
         return nullptr;
     }
+    return create_index(K, B, R, m, eta, seed, flags, nullptr);
+}
+
+rambo_s *rambo::create_index(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed,
+                             uint32_t flags, const uint64_t *gids) {
     if (K == 0 || K >= (1ULL << 32) || B == 0 || B > RAMBO_MAX_B || R == 0 || R > RAMBO_MAX_R || eta == 0 ||
         eta > RAMBO_MAX_ETA || m == 0 || m > (1ULL << 40)) {
         fail(RAMBO_EINVAL, "rambo_create: parameters out of range (K=%llu B=%u R=%u m=%llu eta=%u)",
@@ -142,6 +155,10 @@ RAMBO_API rambo_t *rambo_create_ex(uint64_t K, uint32_t B, uint32_t R, uint64_t 
     auto *h = new rambo_s();
     h->K = K; h->B = B; h->R = R; h->m = m; h->eta = eta; h->seed = seed;
     h->opaque = (flags & RAMBO_TERMS_OPAQUE) != 0;
+    if (gids) {
+        h->gids.assign(gids, gids + K);
+        h->gid_max = *std::max_element(h->gids.begin(), h->gids.end());
+    }
     uint32_t need = (B + 31) / 32, rw = 1, lg = 0;
     while (rw < need) { rw <<= 1; lg++; }
     h->RW = rw;
@@ -210,7 +227,7 @@ RAMBO_API int rambo_layout(const rambo_t *h, rambo_layout_t *out) {
     out->W = h->W;
     out->index_bytes = h->rows_bytes;
     out->rows = h->rows;
-    out->flags = h->opaque ? RAMBO_TERMS_OPAQUE : 0u;
+    out->flags = (h->opaque ? RAMBO_TERMS_OPAQUE : 0u) | (h->gids.empty() ? 0u : RAMBO_SHARD);
     return RAMBO_OK;
 }
 
@@ -496,6 +513,12 @@ uint64_t header_sum(const FileHeader &h) {
     for (uint64_t i = 0; i < sizeof f / sizeof f[0]; i++) s += mix64(f[i] ^ ((i + 1) << 56));
     return s;
 }
+// a shard's global document ids enter the checksum likewise, each with its place
+uint64_t gids_sum(const std::vector<uint64_t> &g) {
+    uint64_t s = 0;
+    for (uint64_t i = 0; i < g.size(); i++) s += mix64(g[i] + mix64(i ^ (0xABull << 56)));
+    return s;
+}
 
 // Two pinned staging buffers and their events, freed on scope exit.
 struct Staging {
@@ -538,17 +561,20 @@ RAMBO_API int rambo_save(rambo_t *h, const char *path) {
     hd.version = 1;
     hd.header_bytes = sizeof(FileHeader);
     hd.K = h->K; hd.m = h->m; hd.seed = h->seed; hd.rows_bytes = h->rows_bytes;
-    hd.B = h->B; hd.R = h->R; hd.eta = h->eta; hd.flags = h->opaque ? RAMBO_TERMS_OPAQUE : 0u;
+    hd.B = h->B; hd.R = h->R; hd.eta = h->eta;
+    hd.flags = (h->opaque ? RAMBO_TERMS_OPAQUE : 0u) | (h->gids.empty() ? 0u : RAMBO_SHARD);
     hd.row_words = h->RW;
     int st = rows_checksum(h, &hd.checksum, s);
     if (st != RAMBO_OK) return st;
-    hd.checksum += header_sum(hd);
+    hd.checksum += header_sum(hd) + gids_sum(h->gids);
     Staging sg;
     if ((st = sg.init()) != RAMBO_OK) return st;
     File fl;
     fl.f = fopen(path, "wb");
     if (!fl.f) return fail(RAMBO_EIO, "rambo_save: cannot open %s for writing", path);
     if (fwrite(&hd, sizeof hd, 1, fl.f) != 1) return fail(RAMBO_EIO, "rambo_save: write failed (%s)", path);
+    if (!h->gids.empty() && fwrite(h->gids.data(), 8, h->gids.size(), fl.f) != h->gids.size())
+        return fail(RAMBO_EIO, "rambo_save: write failed (%s)", path);
     // chunk k is copied into buffer k & 1 while chunk k - 1 is written out
     const uint64_t n = (h->rows_bytes + kFileChunk - 1) / kFileChunk;
     const char *src = reinterpret_cast<const char *>(h->rows);
@@ -589,8 +615,25 @@ RAMBO_API rambo_t *rambo_load(const char *path) {
         fail(RAMBO_EIO, "rambo_load: %s is not a RAMBO index file (version 1)", path);
         return nullptr;
     }
-    rambo_t *h = rambo_create_ex(hd.K, hd.B, hd.R, hd.m, hd.eta, hd.seed, hd.flags);
-    if (!h) return nullptr;  // status and message from rambo_create_ex
+    if (hd.flags & ~(uint32_t)(RAMBO_TERMS_OPAQUE | RAMBO_SHARD)) {
+        fail(RAMBO_EIO, "rambo_load: %s has unknown flags 0x%x", path, hd.flags);
+        return nullptr;
+    }
+    std::vector<uint64_t> gids;
+    if (hd.flags & RAMBO_SHARD) {
+        if (hd.K == 0 || hd.K >= (1ULL << 32)) {
+            fail(RAMBO_EIO, "rambo_load: %s is not a valid index file", path);
+            return nullptr;
+        }
+        gids.resize(hd.K);
+        if (fread(gids.data(), 8, hd.K, fl.f) != hd.K) {
+            fail(RAMBO_EIO, "rambo_load: %s is shorter than its header says", path);
+            return nullptr;
+        }
+    }
+    rambo_t *h = create_index(hd.K, hd.B, hd.R, hd.m, hd.eta, hd.seed, hd.flags & RAMBO_TERMS_OPAQUE,
+                              gids.empty() ? nullptr : gids.data());
+    if (!h) return nullptr;  // status and message from the creation
     auto drop = [&](int status, const char *msg) -> rambo_t * {
         rambo_destroy(h);
         fail(status, "rambo_load: %s (%s)", msg, path);
@@ -618,7 +661,8 @@ RAMBO_API rambo_t *rambo_load(const char *path) {
     if (fread(&extra, 1, 1, fl.f) != 0) return drop(RAMBO_EIO, "file is longer than its header says");
     uint64_t sum = 0;
     if (rows_checksum(h, &sum, s) != RAMBO_OK) return drop(RAMBO_EDEVICE, "checksum failed");
-    if (sum + header_sum(hd) != hd.checksum) return drop(RAMBO_EIO, "checksum mismatch: the file is corrupted");
+    if (sum + header_sum(hd) + gids_sum(gids) != hd.checksum)
+        return drop(RAMBO_EIO, "checksum mismatch: the file is corrupted");
     ok();
     return h;
 }

@@ -49,6 +49,11 @@ struct rambo_s {
     int device = 0, n_cu = 0;
     uint64_t rows_bytes = 0;
     bool opaque = false;  // documents are sets of opaque 64-bit terms
+    // a shard (Section 5.3): local document l stands for global document
+    // gids[l], whose cells are phi_r(gids[l]); empty for an ordinary index
+    std::vector<uint64_t> gids;
+    uint64_t *d_gids = nullptr;
+    uint64_t gid_max = 0;
     // id-list queries: per-read answer sizes and scan scratch (grown as
     // needed; one id-list query at a time per handle)
     unsigned long long *d_ids_counts = nullptr;
@@ -102,6 +107,10 @@ struct QueryOpts {
     unsigned long long *counts;   // id-list mode: per-read answer sizes, zero answers not written; or null
     unsigned long long *emptyq;   // incremented once per query that has no term (no valid window)
 };
+
+// api.hip: create an index (gids: null, or K global document ids of a shard)
+rambo_s *create_index(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uint32_t eta, uint64_t seed, uint32_t flags,
+                      const uint64_t *gids);
 
 // build.hip
 int launch_build_kmers(rambo_s *h, const uint64_t *kmers, const uint64_t *koff, const uint64_t *doc_ids,

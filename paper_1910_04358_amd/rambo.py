@@ -22,7 +22,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ETRUNC, EBUSY, EIO = 0, -1, -2, -3, -4, -5, -6
 OK_EMPTYQ = 1  # success; some query held no term (answered with every document)
 MODE_PLAIN, MODE_BATCHED = 0, 1
 RESOLVE_AUTO, RESOLVE_DENSE, RESOLVE_CANDIDATE = 0, 1, 2
-TERMS_OPAQUE = 1
+TERMS_OPAQUE, SHARD = 1, 2
 MAX_R, MAX_ETA, MAX_B = 8, 16, 8192
 
 # every function the C ABI exports, with its ctypes signature
@@ -64,6 +64,10 @@ SIGNATURES = {
     "rambo_query_seqs": ([_vp, _vp, _vp, _u64, _vp, _vp], _i32),
     "rambo_query_seqs_ids": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp], _i32),
     "rambo_query_seqs_ids_noalloc": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp], _i32),
+    "rambo_route": ([_vp, _u64, _u32, _u64, _vp, _vp], _i32),
+    "rambo_create_shard": ([_u64, _u32, _u32, _u64, _u32, _u64, _vp], _vp),
+    "rambo_shard_ids": ([_vp, _vp], _i32),
+    "rambo_stack_slice": ([_vp, _vp, _u64, _vp, _u64, _vp], _i32),
     "rambo_set_mode": ([_vp, _i32], _i32),
     "rambo_set_resolve": ([_vp, _i32], _i32),
     "rambo_set_early_exit": ([_vp, _i32], _i32),
@@ -173,6 +177,31 @@ class Rambo:
         L = lib()
         self._adopt(L.rambo_create_ex(K, B, R, m, eta, seed, TERMS_OPAQUE if opaque_terms else 0))
 
+    @classmethod
+    def shard(cls, global_ids, B: int, R: int, m: int, eta: int, seed: int) -> "Rambo":
+        """A shard (Section 5.3) of len(global_ids) local documents; local
+        document l stands for global document global_ids[l]."""
+        g = np.ascontiguousarray(global_ids, dtype=np.uint64)
+        obj = cls.__new__(cls)
+        obj._h = None
+        obj._adopt(lib().rambo_create_shard(g.size, B, R, m, eta, seed, ctypes.c_void_p(g.ctypes.data)))
+        return obj
+
+    def shard_ids(self) -> np.ndarray:
+        out = np.zeros(self.K, dtype=np.uint64)
+        _check(lib().rambo_shard_ids(self._h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def stack_slice(self, slice_, out, stream=None) -> None:
+        """OR this shard's answer rows (local ids) into out at the documents'
+        global ids (out: (n, out_words) int64 device tensor, zeroed by the
+        caller before the first shard)."""
+        n = out.shape[0]
+        if slice_.numel() < n * self.W:
+            raise ValueError("slice too small")
+        _check(lib().rambo_stack_slice(self._h, _dptr(slice_, "slice", _i64()), n, _dptr(out, "out", _i64()),
+                                       out.shape[1], _stream(stream)))
+
     def _adopt(self, h):
         if not h:
             L = lib()
@@ -182,6 +211,7 @@ class Rambo:
         self.K, self.B, self.R, self.m = int(lay.K), int(lay.B), int(lay.R), int(lay.m)
         self.eta, self.seed = int(lay.eta), int(lay.seed)
         self.opaque_terms = bool(lay.flags & TERMS_OPAQUE)
+        self.is_shard = bool(lay.flags & SHARD)
         self.W, self.row_words, self.index_bytes = int(lay.W), int(lay.row_words), int(lay.index_bytes)
 
     # -- index files
@@ -402,6 +432,16 @@ class Rambo:
     def set_tune(self, tune: Tune) -> None:
         t = TuneC(tune.seg, tune.tile, tune.waves_per_cu, tune.wpb, tune.grab, tune.sched, 1)
         _check(lib().rambo_set_tune(self._h, ctypes.byref(t)))
+
+
+def route(doc_ids, G: int, route_seed: int, stream=None):
+    """tau(d) of each document id (device int64 tensor): its shard, as an
+    int32 device tensor (Section 5.3 routing; see rambo_route)."""
+    import torch
+    out = torch.empty(doc_ids.numel(), dtype=torch.int32, device=doc_ids.device)
+    _check(lib().rambo_route(_dptr(doc_ids, "doc_ids", _i64()), doc_ids.numel(), G, route_seed,
+                             _dptr(out, "shard", (torch.int32,)), _stream(stream)))
+    return out
 
 
 def clock() -> float:

@@ -617,3 +617,71 @@ def test_one_repetition_at_a_time_equals_the_whole_oracle():
                 assert _ref.bits_to_ids(out[i], K) == ex, i
     with pytest.raises(ValueError):
         o.build_rep(R, o.new_rep(), docs, L, 0, 1)
+
+
+# ------------------------------------------------ routing and stacking
+def test_two_level_partition_equals_stacked_shards():
+    """Section 5.3: documents are routed to G shards by a random hash tau,
+    each shard is an independent RAMBO of b cells over its documents with the
+    same seeds (so the same Bloom hash functions and the same node-local
+    partition phi_r of the global document id), and the shards stacked are
+    the RAMBO built directly with the two-level partition
+    b * tau(d) + phi_r(d) over B = G * b cells. Checked on the oracle: every
+    BFU of the two-level index is the BFU of its shard, and each document's
+    answer in the two-level index is its answer in its shard, for every read
+    (so the K_g-document answers of the shards, put back in global id order,
+    are the whole answer). An index given phi_r itself as its table equals
+    the plain oracle."""
+    K, G, b, R, m, eta, L, seed, rseed = 300, 4, 6, 3, 1 << 16, 2, 400, 77, 5151
+    dm = gen.DocModel(seed=161, n_docs=K, length=L, docs_per_anc=10, mu_lo=0.02, mu_hi=0.02)
+    docs = dm.docs(0, K)
+    tau = oracle.route(rseed, G, range(K))
+    assert set(tau.tolist()) == set(range(G))
+    local = oracle.Oracle(K, b, R, m, eta, seed, alloc_bits=False)   # phi_r over b cells, global ids
+    phi = local.phis()
+    two = oracle.Oracle(K, G * b, R, m, eta, seed, cells=b * tau[None, :] + phi)
+    two.build_docs(docs, L, 0, K)
+    rm = gen.ReadModel(qseed=162, src_lo=0, src_hi=K, len_kind=1, lo=31, hi=150, err_lo=0.0, err_hi=0.01)
+    reads = gen.reads(dm, rm, 400)
+    want, _ = two.query_seqs(reads.seqs, reads.offsets, oracle.MODE_DEF)
+    assert want.any(axis=1).sum() > 50
+    tbits = two.bits()
+    got = np.zeros_like(want)
+    for g in range(G):
+        gid = np.nonzero(tau == g)[0]
+        sh = oracle.Oracle(gid.size, b, R, m, eta, seed, cells=phi[:, gid])
+        for l, d in enumerate(gid):
+            sh.insert_seq(l, docs[d * L:(d + 1) * L])
+        sbits = sh.bits()
+        for r in range(R):
+            for c in range(b):
+                assert np.array_equal(sbits[r, c], tbits[r, b * g + c]), (g, r, c)
+        ans, _ = sh.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2)
+        abits = np.unpackbits(ans.view(np.uint8), axis=1, bitorder="little")[:, :gid.size]
+        for l, d in enumerate(gid):       # local document l is global document d
+            got[:, d >> 6] |= abits[:, l].astype(np.uint64) << np.uint64(d & 63)
+    assert np.array_equal(got, want)
+    plain = oracle.Oracle(K, b, R, m, eta, seed)
+    table = oracle.Oracle(K, b, R, m, eta, seed, cells=phi)
+    plain.build_docs(docs, L, 0, K)
+    table.build_docs(docs, L, 0, K)
+    assert np.array_equal(plain.bits(), table.bits())
+    assert np.array_equal(table.cells(), phi)
+
+
+def test_two_level_partition_is_two_universal():
+    """Section 5.3's claim: the two-level hash b * tau(d) + phi(d) keeps the
+    collision probability of any two documents at 1/B for B = G * b cells.
+    Over random seeds (routing and index), a fixed pair of document ids
+    collides at that rate; the routing itself spreads documents evenly."""
+    G, b, trials = 4, 8, 6000
+    hits = 0
+    for s in range(trials):
+        t = oracle.route(90_000 + s, G, [17, 901])
+        o = oracle.Oracle(1000, b, 1, 64, 1, 70_000 + s, alloc_bits=False)
+        hits += b * t[0] + o.phi(0, 17) == b * t[1] + o.phi(0, 901)
+    B = G * b
+    assert abs(hits / trials - 1 / B) < 4 * math.sqrt((1 / B) * (1 - 1 / B) / trials), hits / trials
+    cnt = np.bincount(oracle.route(5, G, range(0, 40_000, 3)), minlength=G)
+    exp = cnt.sum() / G
+    assert ((cnt - exp) ** 2 / exp).sum() < G - 1 + 6 * math.sqrt(2 * (G - 1))
