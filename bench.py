@@ -124,11 +124,59 @@ def kmer_queries_run(dev, steps, warmup):
     return rec
 
 
+def rambo_plus(idx, step, dev):
+    """What RAMBO+ (Section 5.1, query time speedup: in repetition r test only
+    the BFUs holding documents the earlier repetitions returned) could save on
+    this batch: one plain-form pass with the library's tallies on (scout
+    schedule, early exit; not timed). A probe of repetition r >= 1 could skip
+    the 16-byte row segments (128 cells) and 128-byte lines whose cells hold
+    none of the candidates left by repetitions 0..r-1."""
+    import torch
+    from paper_1910_04358_amd import MODE_PLAIN
+    c = torch.zeros(6, dtype=torch.int64, device=dev)
+    idx.set_mode(MODE_PLAIN)
+    idx.set_sparse_counter(c)
+    step()
+    torch.cuda.synchronize()
+    idx.set_sparse_counter(None)
+    v = [int(x) for x in c.cpu().tolist()]
+    return {"probes_rep_ge1": v[0], "probes_without_candidate_cell": v[1],
+            "frac_probes_skippable": v[1] / max(1, v[0]),
+            "untouched_16B_segment_frac": v[2] / max(1, v[3]),
+            "untouched_128B_line_frac": v[4] / max(1, v[5]),
+            "segments_per_row": v[3] / max(1, v[0]), "lines_per_row": v[5] / max(1, v[0])}
+
+
+def stream_insert(idx, w, dev):
+    """Streaming insertion (Section 3.2): the workload's new documents
+    (ids w.stream_docs) inserted into the built, resident index in one call;
+    returns (ms, k-mers) timed with events around the insertion kernel."""
+    import torch
+    s0, ns = w.stream_docs
+    L = w.docs.length
+    host = torch.empty(ns * L, dtype=torch.uint8, pin_memory=True)
+    w.docs.docs(s0, ns, out=host.numpy())
+    seqs = host.to(dev)
+    offs = up(np.arange(ns + 1, dtype=np.uint64) * np.uint64(L), dev)
+    ids = up(np.arange(s0, s0 + ns, dtype=np.uint64), dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    idx.insert_seqs(ids, seqs, offs)
+    e1.record()
+    idx.sync()
+    ms = e0.elapsed_time(e1)
+    del seqs, host
+    return ms, ns * (L - 30)
+
+
 def k101000_run(dev, steps, warmup):
     """One GPU's share of a cluster-scale index: K = 101,000 capacity, 1,000
     ancestors x 100 mutants of 100 kbp (1 %), R=6, B=1,000, m=2^27, eta=2
-    (96 GiB); build of 100,000 documents (10^10 k-mers), then 10^6 reads of
-    U(100, 1000) bp (70 % from documents with 1 % errors), batched form,
+    (96 GiB); build of 100,000 documents (10^10 k-mers), streaming insertion
+    of 1,000 new documents (10 new ancestors x 100 mutants, ids 100,000 ..
+    100,999) into the built index, then 10^6 reads of U(100, 1000) bp (70 %
+    from any of the 101,000 documents with 1 % errors), batched form,
     answered as bitsets and as document-id lists."""
     import torch
     import gen
@@ -136,6 +184,8 @@ def k101000_run(dev, steps, warmup):
 
     w = gen.workload(5)
     idx, build_ms, build_kmers = build_index(w, dev, docs_per_chunk=2000)
+    ins_ms, ins_kmers = stream_insert(idx, w, dev)
+    log("K101000: streamed %d new documents (%d k-mers) in %.2f ms" % (w.stream_docs[1], ins_kmers, ins_ms))
     reads = gen.reads(w.docs, w.reads, w.n_reads)
     n_kmers = reads.n_windows()
     seqs, offs = up(reads.seqs, dev), up(reads.offsets, dev)
@@ -156,11 +206,19 @@ def k101000_run(dev, steps, warmup):
     issued = int(probes.item())
     idx.set_probe_counter(None)
     ids_ms = time_steps(lambda: idx.query_seqs_ids(seqs, offs, ids_cap=50_000_000, scratch=out, check=False), 3, 1)
+    rplus = rambo_plus(idx, step, dev)
+    log("K101000: RAMBO+ could skip %.4f of the probes of repetitions >= 1, %.4f of their 16-byte segments"
+        % (rplus["frac_probes_skippable"], rplus["untouched_16B_segment_frac"]))
     rec = {"workload": w.name, "index_bytes": idx.index_bytes, "build_ms": build_ms,
-           "build_input_GBps_u64_kmers": build_kmers * 8 / build_ms / 1e6, "reads": reads.n, "kmers": n_kmers,
+           "build_input_GBps_u64_kmers": build_kmers * 8 / build_ms / 1e6,
+           "stream_insert": {"docs": w.stream_docs[1], "kmers": ins_kmers, "ms": ins_ms,
+                             "kmer_per_s": ins_kmers / ins_ms * 1e3,
+                             "input_GBps_u64_kmers": ins_kmers * 8 / ins_ms / 1e6,
+                             "bases_per_s": w.stream_docs[1] * w.docs.length / ins_ms * 1e3},
+           "reads": reads.n, "kmers": n_kmers,
            "plain_ms": plain_ms, "batched_ms": ms, "kmer_per_s": n_kmers / ms * 1e3, "reads_per_s": reads.n / ms * 1e3,
            "probes": issued, "row_bytes": idx.row_words * 4, "rows_per_s": issued / ms * 1e3,
-           "ids_ms": ids_ms, "tune": idx.get_tune().__dict__}
+           "ids_ms": ids_ms, "rambo_plus": rplus, "tune": idx.get_tune().__dict__}
     log("K101000: build %.0f ms (%.3g k-mer/s); plain %.2f ms, batched %.2f ms per 10^6 reads (%.3g k-mer/s, %.3g rows "
         "of %d B/s); as id lists %.2f ms" % (build_ms, build_kmers / build_ms * 1e3, plain_ms, ms, rec["kmer_per_s"],
                                             rec["rows_per_s"], rec["row_bytes"], ids_ms))
@@ -288,6 +346,8 @@ def main():
     ap.add_argument("--no-kmers", action="store_true", help="skip the single k-mer query workload")
     ap.add_argument("--no-terms", action="store_true", help="skip the word-term (web document) workloads")
     ap.add_argument("--no-k101000", action="store_true", help="skip the K=101,000 (96 GiB) workload")
+    ap.add_argument("--k101000-only", action="store_true",
+                    help="run only the K=101,000 workload and print its record (for profiler runs)")
     ap.add_argument("--no-full", action="store_true", help="skip the runs without early exit")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a 1 GiB device copy (scale for hardware byte counters)")
@@ -306,6 +366,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.k101000_only:
+        print(json.dumps({"k101000": k101000_run(dev, args.steps, args.warmup)}), flush=True)
+        return
     w = gen.workload(3)
     log("workload", w.name)
     idx, build_ms, build_kmers = build_index(w, dev)
@@ -423,6 +486,13 @@ def main():
     except (RuntimeError, OSError) as e:
         log("random-read ceiling not measured:", e)
 
+    rplus = None
+    if args.only is None:
+        rplus = rambo_plus(idx, step, dev)
+        idx.set_mode(MODE_BATCHED)
+        log("RAMBO+ could skip %.4f of the probes of repetitions >= 1, %.4f of their 16-byte segments"
+            % (rplus["frac_probes_skippable"], rplus["untouched_16B_segment_frac"]))
+
     if args.pmc_copy:
         from paper_1910_04358_amd import micro
         ms = micro.copy(1 << 30)
@@ -483,6 +553,7 @@ def main():
         "cpu_baseline": cpu,
         "served": served,
         "no_early_exit": full,
+        "rambo_plus": rplus,
         "kmer_queries": kq,
         "web_terms": web,
     }

@@ -362,6 +362,20 @@ int rambo_set_early_exit(rambo_t *h, int on);
  * to (NULL disables counting). Owned by the caller; one uint64. */
 int rambo_set_probe_counter(rambo_t *h, uint64_t *device_counter);
 
+/* RAMBO+ measurement (Section 5.1, query time speedup: in repetition r only
+ * the BFUs that hold documents returned by the earlier repetitions need a
+ * test). With device_counters set (6 uint64 device words, owned by the
+ * caller; NULL disables), plain-form sequence queries under schedules 1 and
+ * 2 (rambo_tune_t.sched) also tally, before each step of repetitions
+ * 1..R-1, what probes restricted to such BFUs could skip: [0] += probes of
+ * repetitions >= 1, [1] += those whose row holds no candidate cell, [2] +=
+ * 16-byte row segments (128 cells) holding no candidate cell, [3] += row
+ * segments probed, [4] += 128-byte lines holding none, [5] += lines probed;
+ * the candidates of repetition r being the documents whose cells are set in
+ * the read's running masks of repetitions 0..r-1. The answers are
+ * unchanged; the tallies make the queries much slower (measurement only). */
+int rambo_set_sparse_counter(rambo_t *h, uint64_t *device_counters);
+
 /* Launch shape of the batched form (RAMBO_MODE_BATCHED). */
 typedef struct {
     int seg;          /* 32-bit row words one lane reads: 1, 2 or 4 (row split

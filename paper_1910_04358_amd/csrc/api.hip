@@ -474,6 +474,14 @@ RAMBO_API int rambo_set_early_exit(rambo_t *h, int on) {
     return RAMBO_OK;
 }
 
+RAMBO_API int rambo_set_sparse_counter(rambo_t *h, uint64_t *device_counters) {
+    if (!h) return fail(RAMBO_EINVAL, "rambo_set_sparse_counter: null handle");
+    std::lock_guard<std::mutex> g(h->mu);
+    h->sparse_counter = (unsigned long long *)device_counters;
+    drop_graphs(h);
+    return RAMBO_OK;
+}
+
 RAMBO_API int rambo_set_probe_counter(rambo_t *h, uint64_t *device_counter) {
     if (!h) return fail(RAMBO_EINVAL, "rambo_set_probe_counter: null handle");
     std::lock_guard<std::mutex> g(h->mu);

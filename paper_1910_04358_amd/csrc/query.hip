@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_query_kmers(Index ix, const uint64_t *_
 // -------------------------------------------------------------------------
 // sequence queries, plain form: one wave per read, 64 windows per step
 // -------------------------------------------------------------------------
-template <int SEG, int G>
+template <int SEG, int G, bool RPLUS>
 __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_t *__restrict__ seqs,
                                                           const uint64_t *__restrict__ offs, uint64_t n,
                                                           const InputHdr *hdr, uint64_t *__restrict__ out,
@@ -185,8 +185,8 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
     const uint64_t nwin = end - beg >= 31 ? end - beg - 30 : 0;
 
     init_masks(ix, M, lane);
-    const uint64_t issued =
-        probe_windows<SEG, G>(ix, seqs, beg, end, 0, nwin, lane, M, opt.early_exit != 0, opt.sched, stage);
+    const uint64_t issued = probe_windows<SEG, G, RPLUS>(ix, seqs, beg, end, 0, nwin, lane, M, opt.early_exit != 0,
+                                                         opt.sched, stage, opt.rplus);
     if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
     // every valid window is probed at least in repetition 0 unless a probe
     // has ended the read first, so nothing issued means no valid window
@@ -315,10 +315,16 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
     // id-list mode counts queries without a term in the word after the n
     // answer sizes (the caller zeroes it), bitset mode in the handle
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, sched, counts, counts ? counts + n : h->d_emptyq};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, sched, counts, counts ? counts + n : h->d_emptyq,
+                  h->sparse_counter};
+    // the RAMBO+ tallies have a kernel of their own (measurement only)
 #define RAMBO_SPLIT_BODY_                                                                                  \
-    hipLaunchKernelGGL((k_query_seqs_plain<SEG, G>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, seqs, offs, \
-                       n, hdr, out, opt, use_res)
+    if (opt.rplus)                                                                                         \
+        hipLaunchKernelGGL((k_query_seqs_plain<SEG, G, true>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix,  \
+                           seqs, offs, n, hdr, out, opt, use_res);                                          \
+    else                                                                                                   \
+        hipLaunchKernelGGL((k_query_seqs_plain<SEG, G, false>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, ix, \
+                           seqs, offs, n, hdr, out, opt, use_res)
     RAMBO_DISPATCH_SPLIT(seg, G)
 #undef RAMBO_SPLIT_BODY_
     HIP_CHECK(hipGetLastError());

@@ -456,6 +456,73 @@ __device__ __forceinline__ uint32_t opaque_zero(uint64_t x) {
     return z;
 }
 
+// bit b of the B-bit mask M (LDS)
+__device__ __forceinline__ uint32_t mask_bit(const uint32_t *M, uint32_t b) {
+    return (M[b >> 5] >> (b & 31)) & 1u;
+}
+
+// RAMBO+ (Section 5.1, query time speedup): in repetition r only the BFUs
+// that hold documents returned by the earlier repetitions need a test. For a
+// step about to probe repetitions 1..R-1 of its nv valid windows (eta rows
+// each), count how much of each probed row a probe restricted to those BFUs
+// could leave unread: the candidates of repetition r are the documents whose
+// cells are set in the running masks of repetitions 0..r-1; a 16-byte row
+// segment (128 cells) or a 128-byte line (1,024 cells) holding none of their
+// repetition-r cells would not be read. Adds, over repetitions r >= 1:
+// rplus[0] probes, [1] probes whose row holds no candidate cell, [2]
+// untouched 16-byte segments, [3] segments probed, [4] untouched 128-byte
+// lines, [5] lines probed. Measurement only (every candidate's cell record is
+// read once per step); called by all lanes.
+__device__ __forceinline__ void rplus_tally(const Index &ix, const uint32_t *M, uint32_t lane, uint64_t nv,
+                                            unsigned long long *rplus) {
+    uint64_t segs[MAXR];  // per repetition, bit s: segment s holds a candidate cell
+#pragma unroll
+    for (int r = 0; r < MAXR; r++) segs[r] = 0;
+    for (uint32_t c0 = 0; c0 < ix.B; c0 += 64) {
+        const uint32_t b = c0 + lane;
+        uint64_t todo = __ballot(b < ix.B && mask_bit(M, b));
+        while (todo) {
+            const uint32_t cb = c0 + (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t beg = ix.boff[cb], len = ix.boff[cb + 1] - beg;
+            for (uint32_t k = lane; k < len; k += 64) {
+                const uint4 cd = ix.cells[ix.bdoc[beg + k]];
+                bool alive = true;
+#pragma unroll
+                for (int r = 1; r < MAXR; r++) {
+                    if (r < (int)ix.R && alive) {
+                        const uint32_t c = cell_at(cd, r);
+                        segs[r] |= 1ULL << (c >> 7);
+                        alive = mask_bit(M + r * ix.RW, c) != 0;
+                    }
+                }
+            }
+        }
+    }
+    const uint32_t nseg = ix.RW >= 4 ? ix.RW / 4 : 1, nline = ix.RW >= 32 ? ix.RW / 32 : 1;
+    uint64_t c[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int r = 1; r < MAXR; r++) {
+        if (r < (int)ix.R) {
+            uint64_t s = segs[r];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s |= __shfl_xor(s, off);
+            uint32_t lines = 0;
+            for (uint32_t l = 0; l < nline; l++) lines += ((s >> (8 * l)) & 0xFFull) != 0;
+            const uint64_t pr = nv * ix.eta;
+            c[0] += pr;
+            c[1] += s == 0 ? pr : 0;
+            c[2] += pr * (nseg - (uint32_t)__popcll(s));
+            c[3] += pr * nseg;
+            c[4] += pr * (nline - lines);
+            c[5] += pr * nline;
+        }
+    }
+    if (lane == 0)
+        for (int k = 0; k < 6; k++)
+            if (c[k]) atomicAdd(rplus + k, (unsigned long long)c[k]);
+}
+
 // Probe schedules of a read's windows (all give the same running masks)
 enum : int {
     SCHED_STEP = 0,   // per step of 64 windows: repetition 0, then the others
@@ -553,10 +620,13 @@ __device__ __forceinline__ StepBytes load_bytes(const uint8_t *__restrict__ seqs
 // the scout pass has probed and ANDed into M already. The next step's bytes
 // are loaded while the current step probes. Returns the number of (window,
 // repetition) probes the wave issued.
-template <int SEG, int G>
+// With RPLUS, the sweep and scout schedules also tally, before each step of
+// the other repetitions, what a RAMBO+ probe could skip (rplus_tally).
+template <int SEG, int G, bool RPLUS = false>
 __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t *__restrict__ seqs, uint64_t beg,
                                                   uint64_t end, uint64_t w_lo, uint64_t w_hi, uint32_t lane,
-                                                  uint32_t *M, bool early_exit, int sched, uint8_t *stage) {
+                                                  uint32_t *M, bool early_exit, int sched, uint8_t *stage,
+                                                  unsigned long long *rplus = nullptr) {
     uint64_t issued = 0;
     const bool scout = sched == SCHED_SCOUT && stage != nullptr && w_lo < w_hi;
     // Repetition 0 skips the scout windows: those of this span after the
@@ -608,6 +678,7 @@ __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t
             const Window wv = extract_windows(cur.c0, cur.c1, lane);
             const bool valid = wv.valid && (w + lane < w_hi);
             const uint64_t nv = (uint64_t)__popcll(__ballot(valid));
+            if constexpr (RPLUS) rplus_tally(ix, M, lane, nv, rplus);
             bool alive = probe_group<SEG, G, 1, 4>(ix, step_params(ix), wv, valid, lane, M);
             issued += nv * (min(ix.R, 5u) - 1);
             if ((int)ix.R > 5 && (alive || !early_exit)) {
@@ -656,9 +727,6 @@ __device__ __forceinline__ uint32_t cell_mask(const Index &ix, uint32_t wi) {
     return (1u << (ix.B - lo)) - 1u;
 }
 
-__device__ __forceinline__ uint32_t mask_bit(const uint32_t *M, uint32_t b) {
-    return (M[b >> 5] >> (b & 31)) & 1u;
-}
 
 // Document d's cells are all set in the masks M (repetitions FIRST..R-1).
 template <int FIRST>

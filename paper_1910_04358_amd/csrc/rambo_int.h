@@ -70,6 +70,7 @@ struct rambo_s {
     std::vector<uint32_t> phi;  // [R][K]
     int mode = RAMBO_MODE_PLAIN, resolve = RAMBO_RESOLVE_AUTO, early_exit = 1;
     unsigned long long *probe_counter = nullptr;
+    unsigned long long *sparse_counter = nullptr;  // RAMBO+ tallies, 6 words (rambo_set_sparse_counter)
     bool tuned = false;
     rambo::Tune tune;
     hipStream_t aux = nullptr;  // internal stream (graph capture, sync helpers)
@@ -106,6 +107,7 @@ struct QueryOpts {
     int sched;                    // probe schedule (SCHED_*)
     unsigned long long *counts;   // id-list mode: per-read answer sizes, zero answers not written; or null
     unsigned long long *emptyq;   // incremented once per query that has no term (no valid window)
+    unsigned long long *rplus;    // RAMBO+ tallies (plain form, sweep/scout schedules), or null
 };
 
 // api.hip: create an index (gids: null, or K global document ids of a shard)

@@ -4,16 +4,21 @@
 // Requests wait in a host queue. A dispatcher thread forms a batch from
 // everything pending that fits a free staging slot and the admission budget
 // (device bytes of the in-flight reads and their result state), copies it
-// to the slot's device buffers on the slot's own stream and replays the
-// slot's captured batched-query graphs; up to `slots` batches are in flight
-// at once, so the copies of one batch overlap the kernels of another and
-// reads that arrive while others run join the next batch. A completion
-// thread waits for each batch in order, copies its results back and stamps
-// the completion time. Each result is the same bitset rambo_query_seqs gives
-// for that read alone: reads are independent within a batch.
+// on the slot's own stream; up to `slots` batches are in flight at once, so
+// the work of one batch overlaps that of another and reads that arrive while
+// others run join the next batch. Batches below direct_below reads are read
+// by the kernel straight from the slot's pinned staging area and answered
+// straight into its pinned result area (no copy operations: one launch per
+// batch); larger ones are copied to the device and replayed from the slot's
+// captured persistent-form graphs, their results copied back. A completion
+// thread takes each batch as soon as it is done (in any order), hands its
+// results over and stamps the completion time. Each result is the same
+// bitset rambo_query_seqs gives for that read alone: reads are independent
+// within a batch.
 //
 // The serial policy is the one-batch-at-a-time baseline: take everything
 // that has arrived, run the plain kernel, wait, repeat.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -49,6 +54,9 @@ struct Slot {
     hipEvent_t done = nullptr;
     uint8_t *h_stage = nullptr, *d_stage = nullptr;
     uint64_t *h_out = nullptr, *d_out = nullptr;
+    // the pinned staging and result areas as the device addresses them
+    uint8_t *hd_stage = nullptr;
+    uint64_t *hd_out = nullptr;
     std::shared_ptr<BatchGraph> small, large;  // plain-kernel graph for small batches, persistent for large
     std::vector<Request> reqs;
     uint64_t budget = 0;
@@ -103,7 +111,9 @@ static void server_fail(rambo_server_s *s, int st) {
 }
 
 // Pack the slot's requests into its staging area; returns the bytes to copy.
-static uint64_t pack_slot(Slot &sl) {
+// The header points at the batch where the kernels will read it: in the
+// device copy (base = d_stage), or in the pinned area itself (hd_stage).
+static uint64_t pack_slot(Slot &sl, const uint8_t *base) {
     const uint64_t n = sl.reqs.size();
     uint64_t *offs = (uint64_t *)(sl.h_stage + kHdrBytes);
     uint8_t *bytes = (uint8_t *)(offs + n + 1);
@@ -116,26 +126,45 @@ static uint64_t pack_slot(Slot &sl) {
     }
     InputHdr *hdr = (InputHdr *)sl.h_stage;
     hdr->n = n;
-    hdr->offs = (const uint64_t *)(sl.d_stage + kHdrBytes);
-    hdr->seqs = sl.d_stage + kHdrBytes + (n + 1) * 8;
+    hdr->offs = (const uint64_t *)(base + kHdrBytes);
+    hdr->seqs = base + kHdrBytes + (n + 1) * 8;
     hdr->pad = 0;
     return kHdrBytes + (n + 1) * 8 + off;
 }
 
-static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n, uint64_t copy_bytes) {
+// Whether the continuous policy serves an n-read batch from the pinned areas
+// directly (the plain kernel launched directly, or the slot's plain-kernel
+// graph, both reading the pinned staging area and writing the pinned result
+// area) rather than through device copies and the persistent form.
+static bool zero_copy(const rambo_server_s *s, const Slot &sl, uint64_t n) {
+    return s->cfg.policy == RAMBO_SERVE_CONTINUOUS && (n < s->cfg.direct_below || n <= sl.small->cap);
+}
+
+static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n) {
     rambo_s *h = s->h;
-    HIP_CHECK(hipMemcpyAsync(sl.d_stage, sl.h_stage, copy_bytes, hipMemcpyHostToDevice, sl.stream));
+    const bool zc = zero_copy(s, sl, n);
+    const uint64_t copy_bytes = pack_slot(sl, zc ? sl.hd_stage : sl.d_stage);
     int st;
-    if (s->cfg.policy == RAMBO_SERVE_SERIAL || n < s->cfg.direct_below) {
-        const uint64_t *offs = (const uint64_t *)(sl.d_stage + kHdrBytes);
-        st = launch_query_seqs_plain(h, sl.d_stage + kHdrBytes + (n + 1) * 8, offs, n, sl.d_out, sl.stream,
+    if (zc && n < s->cfg.direct_below) {
+        // one launch: reads from the staging area, answers into the result area
+        const uint8_t *base = sl.hd_stage + kHdrBytes;
+        st = launch_query_seqs_plain(h, base + (n + 1) * 8, (const uint64_t *)base, n, sl.hd_out, sl.stream,
                                      default_seg(h->RW));
+    } else if (zc) {
+        st = launch_batch_graph(h, *sl.small, sl.stream);
     } else {
-        BatchGraph &bg = (n <= sl.small->cap) ? *sl.small : *sl.large;
-        st = launch_batch_graph(h, bg, sl.stream);
+        HIP_CHECK(hipMemcpyAsync(sl.d_stage, sl.h_stage, copy_bytes, hipMemcpyHostToDevice, sl.stream));
+        if (s->cfg.policy == RAMBO_SERVE_SERIAL) {
+            const uint64_t *offs = (const uint64_t *)(sl.d_stage + kHdrBytes);
+            st = launch_query_seqs_plain(h, sl.d_stage + kHdrBytes + (n + 1) * 8, offs, n, sl.d_out, sl.stream,
+                                         default_seg(h->RW));
+        } else {
+            st = launch_batch_graph(h, *sl.large, sl.stream);
+        }
+        if (st == RAMBO_OK)
+            HIP_CHECK(hipMemcpyAsync(sl.h_out, sl.d_out, n * h->W * 8, hipMemcpyDeviceToHost, sl.stream));
     }
     if (st != RAMBO_OK) return st;
-    HIP_CHECK(hipMemcpyAsync(sl.h_out, sl.d_out, n * h->W * 8, hipMemcpyDeviceToHost, sl.stream));
     HIP_CHECK(hipEventRecord(sl.done, sl.stream));
     return RAMBO_OK;
 }
@@ -192,7 +221,7 @@ static void dispatcher_main(rambo_server_s *s) {
         Slot &sl = s->slots[slot];
         sl.budget = cost;
         sl.t_admit = now_s();
-        int st = launch_slot(s, sl, n, pack_slot(sl));
+        int st = launch_slot(s, sl, n);
         if (st != RAMBO_OK) {
             server_fail(s, st);
             return;
@@ -213,8 +242,8 @@ static void dispatcher_main(rambo_server_s *s) {
 static void completer_main(rambo_server_s *s) {
     (void)hipSetDevice(s->h->device);
     const uint64_t W = s->h->W;
+    std::vector<int> look;
     for (;;) {
-        int slot;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_done.wait(lk, [&] { return !s->inflight.empty() || (s->stopping && s->pending.empty()) || s->error; });
@@ -222,17 +251,27 @@ static void completer_main(rambo_server_s *s) {
                 if (s->stopping) return;
                 continue;
             }
-            slot = s->inflight.front();
+            look.assign(s->inflight.begin(), s->inflight.end());
+        }
+        // the first in-flight batch found done, in any order (spinning on the
+        // events: completion latency matters more than one host core)
+        int slot = -1;
+        for (size_t k = 0; slot < 0; k = (k + 1) % look.size()) {
+            const hipError_t e = hipEventQuery(s->slots[look[k]].done);
+            if (e == hipSuccess) {
+                slot = look[k];
+            } else if (e != hipErrorNotReady) {
+                fail(RAMBO_EDEVICE, "server: batch failed: %s", hipGetErrorString(e));
+                server_fail(s, RAMBO_EDEVICE);
+                return;
+            } else if (k + 1 == look.size()) {
+                std::this_thread::yield();
+                // batches dispatched meanwhile join the polling
+                std::lock_guard<std::mutex> g(s->mu);
+                look.assign(s->inflight.begin(), s->inflight.end());
+            }
         }
         Slot &sl = s->slots[slot];
-        // spin on the event: completion latency matters more than one host core
-        hipError_t e;
-        while ((e = hipEventQuery(sl.done)) == hipErrorNotReady) std::this_thread::yield();
-        if (e != hipSuccess) {
-            fail(RAMBO_EDEVICE, "server: batch failed: %s", hipGetErrorString(e));
-            server_fail(s, RAMBO_EDEVICE);
-            return;
-        }
         const double t_done = now_s();
         {
             std::lock_guard<std::mutex> g(s->cmu);
@@ -251,7 +290,7 @@ static void completer_main(rambo_server_s *s) {
         s->cv_poll.notify_all();
         {
             std::lock_guard<std::mutex> g(s->mu);
-            s->inflight.pop_front();
+            s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), slot));
             s->budget_used -= sl.budget;
             s->stats.completed += sl.reqs.size();
             sl.reqs.clear();
@@ -324,16 +363,29 @@ static int setup_slot(rambo_server_s *s, Slot &sl) {
     HIP_CHECK(hipHostMalloc((void **)&sl.h_out, R * h->W * 8, hipHostMallocDefault));
     HIP_CHECK(hipMalloc(&sl.d_stage, stage));
     HIP_CHECK(hipMalloc(&sl.d_out, R * h->W * 8));
+    HIP_CHECK(hipHostGetDevicePointer((void **)&sl.hd_stage, sl.h_stage, 0));
+    HIP_CHECK(hipHostGetDevicePointer((void **)&sl.hd_out, sl.h_out, 0));
     if (s->cfg.policy == RAMBO_SERVE_CONTINUOUS) {
-        const InputHdr *in = (const InputHdr *)sl.d_stage;
         Tune large = h->tune;
         if (!h->tuned) large.seg = default_seg(h->RW);
-        // small batches: the plain kernel, one wave per read; large ones:
-        // the persistent form with the handle's tuned shape
+        // small batches: the plain kernel, one wave per read, on the pinned
+        // areas; large ones: the persistent form with the handle's tuned
+        // shape on the device copy
         const uint64_t small_cap = std::min<uint64_t>(R, 2048);
-        int st = make_plain_graph(h, in, small_cap, sl.d_out, sl.small);
-        if (st == RAMBO_OK) st = make_batch_graph(h, large, in, nullptr, R, sl.d_out, sl.large);
+        int st = make_plain_graph(h, (const InputHdr *)sl.hd_stage, small_cap, sl.hd_out, sl.small);
+        if (st == RAMBO_OK)
+            st = make_batch_graph(h, large, (const InputHdr *)sl.d_stage, nullptr, R, sl.d_out, sl.large);
         if (st != RAMBO_OK) return st;
+        // replay both graphs once on an empty batch, so that the first real
+        // batch does not pay for loading their kernels
+        InputHdr *hdr = (InputHdr *)sl.h_stage;
+        hdr->n = 0;
+        hdr->offs = (const uint64_t *)(sl.hd_stage + kHdrBytes);
+        hdr->seqs = sl.hd_stage + kHdrBytes;
+        HIP_CHECK(hipMemcpy(sl.d_stage, sl.h_stage, sizeof(InputHdr), hipMemcpyHostToDevice));
+        if ((st = launch_batch_graph(h, *sl.small, sl.stream)) != RAMBO_OK) return st;
+        if ((st = launch_batch_graph(h, *sl.large, sl.stream)) != RAMBO_OK) return st;
+        HIP_CHECK(hipStreamSynchronize(sl.stream));
     }
     return RAMBO_OK;
 }

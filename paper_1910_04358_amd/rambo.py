@@ -72,6 +72,7 @@ SIGNATURES = {
     "rambo_set_resolve": ([_vp, _i32], _i32),
     "rambo_set_early_exit": ([_vp, _i32], _i32),
     "rambo_set_probe_counter": ([_vp, _vp], _i32),
+    "rambo_set_sparse_counter": ([_vp, _vp], _i32),
     "rambo_autotune": ([_vp, _vp, _vp, _u64, _vp, _vp], _i32),
     "rambo_get_tune": ([_vp, ctypes.POINTER(TuneC)], _i32),
     "rambo_set_tune": ([_vp, ctypes.POINTER(TuneC)], _i32),
@@ -405,6 +406,16 @@ class Rambo:
     def set_probe_counter(self, counter) -> None:
         ptr = None if counter is None else _dptr(counter, "counter", _i64())
         _check(lib().rambo_set_probe_counter(self._h, ptr))
+
+    def set_sparse_counter(self, counters) -> None:
+        """RAMBO+ tallies (6 int64 words on the device; None disables); see
+        rambo_set_sparse_counter."""
+        ptr = None
+        if counters is not None:
+            if counters.numel() < 6:
+                raise ValueError("the sparse counter needs 6 words")
+            ptr = _dptr(counters, "counters", _i64())
+        _check(lib().rambo_set_sparse_counter(self._h, ptr))
 
     def sync(self, stream=None) -> int:
         """Wait for the handle's work on the stream; returns OK, or OK_EMPTYQ if

@@ -428,3 +428,51 @@ def test_empty_query_status():
     idx.query_term_sets(to_dev(t), to_dev(np.array([0, 1, 3], dtype=np.uint64)))
     assert idx.sync() == rb.OK
     idx.set_mode(rb.MODE_PLAIN)
+
+
+def test_rambo_plus_tallies_exact_for_two_repetitions():
+    """The RAMBO+ tallies (Section 5.1, query time speedup) on an index
+    where they have a closed form: with R = 2 and repetition 0 swept over the
+    whole read first (schedules 1 and 2), the candidates of repetition 1 are
+    the documents of the cells of repetition 0 whose BFU holds every term of
+    the read -- from the oracle's own filters -- and every step of
+    repetition 1 sees the same candidate cells, so a read adds (valid
+    windows) x eta x (rows' 16-byte segments, lines) untouched by their
+    repetition-1 cells. Rows of 256 cells: two segments, one line. Answers
+    are unchanged with the tallies on."""
+    import torch
+    K, B, R, m, eta, seed = 600, 256, 2, 1 << 20, 2, 4343
+    dm = gen.DocModel(seed=191, n_docs=K, length=4_000, docs_per_anc=60, mu_lo=0.01, mu_hi=0.01)
+    rm = gen.ReadModel(qseed=192, src_lo=0, src_hi=K, len_kind=0, median=150, sigma=0.8, lo=31, hi=1500,
+                       err_lo=0.0, err_hi=0.0)
+    idx = rb.Rambo(K, B, R, m, eta, seed)
+    build_gpu_seqs(idx, dm, 0, K)
+    o = build_oracle((K, B, R, m, eta, seed), dm)
+    reads = gen.reads(dm, rm, 60)
+    want, _ = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2)
+    bits, cells = o.bits(), o.cells()
+    exp = np.zeros(6, dtype=np.int64)
+    for i in range(reads.n):
+        s = reads.read(i)
+        nvalid = _ref.seq_terms(s).size
+        pos0 = [b for b in range(B) if o.bfu_test_seq(0, bits[0, b], s)]
+        cand = np.nonzero(np.isin(cells[0], pos0))[0]
+        touched = {int(cells[1, d]) >> 7 for d in cand}
+        pr = nvalid * eta
+        exp += [pr, pr if not touched else 0, pr * (2 - len(touched)), pr * 2, pr * (1 if not touched else 0), pr]
+    assert exp[0] > 0 and exp[2] > 0  # some candidate sets leave a segment untouched
+    counters = torch.zeros(6, dtype=torch.int64, device="cuda")
+    seqs, offs = reads_to_dev(reads)
+    idx.set_early_exit(False)
+    idx.set_mode(rb.MODE_PLAIN)
+    for sched in (1, 2):
+        t = idx.get_tune()
+        t.sched = sched
+        idx.set_tune(t)
+        counters.zero_()
+        idx.set_sparse_counter(counters)
+        got = to_host_u64(idx.query_seqs(seqs, offs))
+        idx.set_sparse_counter(None)
+        assert np.array_equal(got, want)
+        assert counters.cpu().numpy().tolist() == exp.tolist(), sched
+    idx.close()
