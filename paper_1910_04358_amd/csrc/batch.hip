@@ -348,7 +348,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
     if (opt.probes && lane == 0 && issued) atomicAdd(opt.probes, (unsigned long long)(issued * ix.eta));
 }
 
-static constexpr uint32_t kMaxLds = 64 * 1024;
 
 static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *out, unsigned long long *counts,
                         hipStream_t s) {
@@ -388,12 +387,8 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
     const int G = (int)h->RW / tu.seg;
-    int use_res = 1;
-    size_t lds = (size_t)tu.wpb * wave_lds(mw, h->W, true, false).total * 4;
-    if (lds > kMaxLds) {
-        use_res = 0;
-        lds = (size_t)tu.wpb * wave_lds(mw, h->W, false, false).total * 4;
-    }
+    const int use_res = seq_lds_result(h->W) ? 1 : 0;
+    const size_t lds = (size_t)tu.wpb * wave_lds(mw, h->W, use_res != 0, false).total * 4;
     // the scout schedule has run its scout windows in the scout pass already
     const int ksched = tu.sched == SCHED_SCOUT ? SCHED_PRESCOUT : tu.sched;
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, ksched, counts, counts ? counts + bg.cap : h->d_emptyq};

@@ -305,12 +305,8 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     const int WPB = 4;
     const int sched = h->tune.sched;  // (this form scouts inside its kernel)
     const bool stage = sched == SCHED_SCOUT;
-    int use_res = 1;
-    size_t lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, true, stage).total * 4;
-    if (lds > kMaxLds) {
-        use_res = 0;
-        lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, false, stage).total * 4;
-    }
+    const int use_res = seq_lds_result(h->W) ? 1 : 0;
+    const size_t lds = (size_t)WPB * wave_lds(h->R * h->RW, h->W, use_res != 0, stage).total * 4;
     const uint64_t blocks = (n + WPB - 1) / WPB;
     if (blocks > 0x7FFFFFFFULL) return fail(RAMBO_EINVAL, "rambo_query_seqs: batch too large");
     // id-list mode counts queries without a term in the word after the n

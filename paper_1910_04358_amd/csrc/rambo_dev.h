@@ -64,6 +64,13 @@ constexpr uint32_t kStageWords = 528;  // 2112 bytes: 64 windows 31 apart, +30, 
 struct WaveLds {
     uint32_t masks, res, stage, total;  // word offsets and size
 };
+// Whether a sequence-query kernel keeps the candidate resolve's bitset in
+// LDS: only for small W. Its 2 W words per wave would otherwise limit the
+// waves a compute unit holds (K = 101,000: 12.6 KB per wave, 8 waves per
+// CU); without it the candidate resolve writes the output row directly,
+// which is slower than the LDS bitset where LDS is plentiful.
+__host__ __device__ inline bool seq_lds_result(uint64_t W) { return W <= 512; }
+
 __host__ __device__ inline WaveLds wave_lds(uint32_t mask_words, uint64_t W, bool use_res, bool stage) {
     WaveLds l;
     l.masks = 0;
@@ -839,6 +846,68 @@ __device__ __forceinline__ uint64_t resolve_candidates(const Index &ix, const ui
     return pc;
 }
 
+// As resolve_candidates, with the answer written straight into the output
+// row instead of an LDS bitset (which would take W words of LDS per wave and
+// limit the waves a compute unit holds): the row is zeroed, and once those
+// stores have completed each kept candidate sets its bit with an atomic OR
+// (the documents of distinct cells are distinct, so each bit is set once).
+// Returns this lane's number of documents kept.
+__device__ __forceinline__ uint64_t resolve_candidates_out(const Index &ix, const uint32_t *M, uint64_t *out,
+                                                           uint32_t lane) {
+    for (uint32_t w = lane; w < ix.W; w += 64) out[w] = 0;
+    // every lane's zeros are performed (acknowledged by L2) before any OR
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    uint64_t kept = 0;
+    for (uint32_t c0 = 0; c0 < ix.B; c0 += 64) {
+        const uint32_t b = c0 + lane;
+        const bool set = b < ix.B && mask_bit(M, b);
+        if (__ballot(set) == 0) continue;
+        uint32_t beg = 0, len = 0;
+        if (set) {
+            beg = ix.boff[b];
+            len = ix.boff[b + 1] - beg;
+        }
+        uint32_t incl = len;  // inclusive prefix sum of len over the lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(incl, off);
+            if ((int)lane >= off) incl += t;
+        }
+        const uint32_t total = __shfl(incl, 63);
+        const uint32_t excl = incl - len;
+        constexpr int U = 4;  // candidates per lane per round trip
+        for (uint32_t k0 = 0; k0 < total; k0 += 64 * U) {
+            uint32_t pos[U];
+            bool has[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t k = k0 + (uint32_t)u * 64 + lane;
+                has[u] = k < total;
+                uint32_t lo = 0;  // owner lane of candidate k (all lanes search)
+#pragma unroll
+                for (uint32_t st = 32; st; st >>= 1)
+                    if (__shfl(incl, (int)(lo + st - 1)) <= k) lo += st;
+                const uint32_t ob = __shfl(beg, (int)lo), oe = __shfl(excl, (int)lo);
+                pos[u] = has[u] ? ob + (k - oe) : 0u;
+            }
+            uint32_t d[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) d[u] = has[u] ? ix.bdoc[pos[u]] : 0u;
+            uint4 cd[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) cd[u] = has[u] ? ix.cells[d[u]] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (has[u] && doc_kept<1>(ix, M, cd[u])) {
+                    atomicOr((unsigned long long *)&out[d[u] >> 6], 1ULL << (d[u] & 63));
+                    kept++;
+                }
+        }
+    }
+    return kept;
+}
+
 // Number of candidates of the repetition-0 cells set in M, estimated from the
 // number of cells (documents spread evenly over the B cells).
 __device__ __forceinline__ uint64_t estimate_candidates(const Index &ix, const uint32_t *M0) {
@@ -847,16 +916,17 @@ __device__ __forceinline__ uint64_t estimate_candidates(const Index &ix, const u
     return cells * ((ix.K + ix.B - 1) / ix.B);
 }
 
-// resolve: 0 auto, 1 dense, 2 candidate (res == nullptr forces dense).
+// resolve: 0 auto, 1 dense, 2 candidate (with res, an LDS bitset of W words,
+// the candidates collect there; without, straight in the output row).
 // Returns the number of documents reported (wave-uniform).
 __device__ __forceinline__ uint64_t resolve(const Index &ix, const uint32_t *M, uint64_t *res, uint64_t *out,
                                             uint32_t lane, int mode) {
     bool cand = false;
-    if (res != nullptr) {
-        if (mode == 2) cand = true;
-        else if (mode == 0) cand = estimate_candidates(ix, M) * (ix.R - 1) * 2 < ix.K * ix.R;
-    }
-    uint64_t pc = cand ? resolve_candidates(ix, M, res, out, lane) : resolve_dense(ix, M, out, lane);
+    if (mode == 2) cand = true;
+    else if (mode == 0) cand = estimate_candidates(ix, M) * (ix.R - 1) * 2 < ix.K * ix.R;
+    uint64_t pc = !cand              ? resolve_dense(ix, M, out, lane)
+                  : res != nullptr ? resolve_candidates(ix, M, res, out, lane)
+                                   : resolve_candidates_out(ix, M, out, lane);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off);
     return pc;

@@ -6,10 +6,18 @@ computes outputs one by one: whole BFUs of sampled cells (built from just the
 documents of the cell, `orc_bfu_insert_seq`), compared bit for bit with the
 GPU index, and the answer for sampled documents on every read (document d is
 reported iff every term of the read passes in BFU(r, phi_r(d)) for all r).
-Properties that hold at any size cover the rest: zero false negatives,
-strand invariance, plain = batched, streaming insertion.
+Expected answers computed beforehand by the oracle one repetition at a time
+(tests/golden/<workload>_answers.txt, written by
+tests/golden/make_fullsize_golden.py, which calls only the oracle) give the
+whole answer of 10,000 sampled reads, and the answers of sampled documents
+(their cells covering every row word or row segment in every repetition)
+on every read of the workload. Properties that hold at any size cover the
+rest: zero false negatives, strand invariance, plain = batched, streaming
+insertion.
 """
 import concurrent.futures as cf
+import hashlib
+import os
 
 import numpy as np
 import pytest
@@ -68,6 +76,35 @@ def bit_of(bits, d):
     return ((bits[:, d >> 6] >> np.uint64(d & 63)) & np.uint64(1)).astype(bool)
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name, reads):
+    """(sampled read indices, {read: ascending ids} for non-empty sampled
+    answers, {doc: set of reads reporting it}) from the stored oracle
+    answers; checks that the workload's reads are the ones they were
+    computed for."""
+    hdr, sample, ans, cols = {}, None, {}, {}
+    for line in open(os.path.join(GOLDEN, "%s_answers.txt" % name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "sample":
+            sample = np.array([int(x) for x in f[1:]], dtype=np.int64)
+        elif f[0] == "A":
+            ans[int(f[1])] = [int(x) for x in f[2:]]
+        elif f[0] == "D":
+            cols[int(f[1])] = {int(x) for x in f[2:]}
+        else:
+            hdr[f[0]] = f[1]
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(reads.offsets, dtype=np.uint64).tobytes())
+    h.update(np.ascontiguousarray(reads.seqs, dtype=np.uint8).tobytes())
+    assert h.hexdigest() == hdr["reads_sha256"], "the workload's reads differ from the stored answers' reads"
+    assert int(hdr["reads"]) == reads.n
+    return sample, ans, cols
+
+
 def test_k1000_kmer_queries_full():
     """K = 1,000 workload in full: the whole index against the oracle's
     (sampled BFUs), 10^7 k-mer queries, 20,000 checked one by one."""
@@ -122,9 +159,20 @@ def test_k10000_reads_full():
     for i in clean:
         d = int(reads.src[i])
         assert (got[i, d >> 6] >> np.uint64(d & 63)) & np.uint64(1), i
-    # sampled documents against the oracle, for every read
+    # the oracle's whole answers for 10,000 sampled reads, and the answers of
+    # sampled documents (covering all four 32-bit row words in every
+    # repetition) on every read
+    sample, ans, cols = load_golden("k10000", reads)
+    assert sample.size == 10_000 and len(ans) > 1000 and len(cols) >= 32
+    for i in sample:
+        assert sorted(_ref.bits_to_ids(got[i], w.K)) == ans.get(int(i), []), int(i)
     o = oracle.Oracle(w.K, w.B, w.R, w.m, w.eta, w.index_seed, alloc_bits=False)
     phis = o.phis()
+    for d, rs in cols.items():
+        assert set(np.nonzero(bit_of(got, d))[0].tolist()) == rs, d
+    assert {int(phis[r, d]) // 32 for d in cols for r in range(w.R)} == {0, 1, 2, 3}
+    # whole BFUs of sampled cells, built by the oracle, and those documents'
+    # answers on every read from them
     docs = [int(reads.src[clean[0]]), 4321, 9876]
     cells = [(r, int(phis[r, d])) for d in docs for r in range(w.R)]
     F = oracle_cells(o, w.docs, cells, w.docs.n_docs, phis)
@@ -195,13 +243,24 @@ def test_k101000_streaming_and_id_lists_full():
         assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(bits[i], idx.K)), i
     # sampled documents against the oracle, for every read
     ans = doc_answers(o, F, phis, docs, reads)
-    for d in docs:
+    read_of = np.repeat(np.arange(reads.n), counts)  # the read each listed id belongs to
+
+    def column(d):
         col = np.zeros(reads.n, dtype=bool)
-        for i in np.nonzero(counts)[0]:
-            lst = ids[id_off[i]:id_off[i + 1]]
-            k = np.searchsorted(lst, d)
-            col[i] = k < lst.size and lst[k] == d
-        assert np.array_equal(col, ans[d]), d
+        col[read_of[ids == d]] = True
+        return col
+    for d in docs:
+        assert np.array_equal(column(d), ans[d]), d
+    # the oracle's whole answers for 10,000 sampled reads, and the answers of
+    # sampled documents (covering all eight 16-byte row segments in every
+    # repetition) on every read
+    sample, gans, gcols = load_golden("k101000", reads)
+    assert sample.size == 10_000 and len(gcols) >= 16
+    for i in sample:
+        assert ids[id_off[i]:id_off[i + 1]].tolist() == gans.get(int(i), []), int(i)
+    for d, rs in gcols.items():
+        assert set(np.nonzero(column(d))[0].tolist()) == rs, d
+    assert {int(phis[r, d]) // 128 for d in gcols for r in range(w.R)} == set(range(8))
     clean = np.nonzero((reads.src >= 0) & (reads.nerr == 0))[0]
     assert clean.size > 1000
     for i in clean[:5000]:

@@ -30,6 +30,12 @@ CASES = {
              gen.DocModel(seed=73, n_docs=2000, length=10_000, docs_per_anc=100, mu_lo=0.01, mu_hi=0.01),
              gen.ReadModel(qseed=83, src_lo=0, src_hi=2000, len_kind=1, lo=100, hi=1000, err_lo=0.01,
                            err_hi=0.01), 2000),
+    # many documents (W = 625 result words): the candidate resolve writes the
+    # output row directly instead of collecting it in LDS
+    "wide": (40_000, 200, 3, 1 << 22, 2,
+             gen.DocModel(seed=75, n_docs=40_000, length=600, docs_per_anc=40, mu_lo=0.01, mu_hi=0.01),
+             gen.ReadModel(qseed=85, src_lo=0, src_hi=40_000, len_kind=1, lo=60, hi=600, err_lo=0.0,
+                           err_hi=0.01), 1500),
 }
 
 _built = {}
@@ -212,7 +218,7 @@ def test_invalid_kmer_values_reported():
         idx.insert(idx.K, np.array([1], dtype=np.uint64))
 
 
-@pytest.mark.parametrize("name", ["rw4", "rw32"])
+@pytest.mark.parametrize("name", ["rw4", "rw32", "wide"])
 def test_id_lists_match_bitsets(name):
     """Id lists in both forms (answer sizes from the query, bitsets written
     only for non-empty answers), twice in a row and mixed with bitset
