@@ -70,6 +70,7 @@ static void free_device(rambo_s *h) {
     if (h->rows) (void)hipFree(h->rows);
     if (h->d_hp) (void)hipFree(h->d_hp);
     if (h->d_cells) (void)hipFree(h->d_cells);
+    if (h->d_cells0) (void)hipFree(h->d_cells0);
     if (h->d_ids_counts) (void)hipFree(h->d_ids_counts);
     if (h->d_ids_aux) (void)hipFree(h->d_ids_aux);
     if (h->d_boff) (void)hipFree(h->d_boff);
@@ -117,6 +118,13 @@ static int upload_tables(rambo_s *h) {
     HIP_CHECK(hipMemcpy(h->d_boff, boff.data(), boff.size() * 4, hipMemcpyHostToDevice));
     HIP_CHECK(hipMalloc(&h->d_bdoc, bdoc.size() * 4));
     HIP_CHECK(hipMemcpy(h->d_bdoc, bdoc.data(), bdoc.size() * 4, hipMemcpyHostToDevice));
+    // the cell records again, in repetition 0's grouping: the candidate
+    // resolve loads a candidate's id and record together
+    std::vector<uint16_t> cells0((size_t)h->K * 8, 0);
+    for (uint64_t k = 0; k < h->K; k++)
+        memcpy(&cells0[k * 8], &cells[(size_t)bdoc[k] * 8], 16);
+    HIP_CHECK(hipMalloc(&h->d_cells0, cells0.size() * 2));
+    HIP_CHECK(hipMemcpy(h->d_cells0, cells0.data(), cells0.size() * 2, hipMemcpyHostToDevice));
     if (!h->gids.empty() && !h->d_gids) {
         HIP_CHECK(hipMalloc(&h->d_gids, h->gids.size() * 8));
         HIP_CHECK(hipMemcpy(h->d_gids, h->gids.data(), h->gids.size() * 8, hipMemcpyHostToDevice));
@@ -294,10 +302,11 @@ RAMBO_API int rambo_fold(rambo_t *h) {
     derive_hashes(h);
     (void)hipFree(h->d_hp);
     (void)hipFree(h->d_cells);
+    (void)hipFree(h->d_cells0);
     (void)hipFree(h->d_boff);
     (void)hipFree(h->d_bdoc);
     h->d_hp = nullptr;
-    h->d_cells = nullptr;
+    h->d_cells = h->d_cells0 = nullptr;
     h->d_boff = h->d_bdoc = nullptr;
     st = upload_tables(h);
     std::lock_guard<std::mutex> g(h->mu);

@@ -33,6 +33,7 @@ struct Index {
     const uint4 *cells;      // [K]      phi_r(d) at 16-bit slot r of record d
     const uint32_t *boff;    // [R][B+1] cell offsets into bdoc
     const uint32_t *bdoc;    // [R][K]   documents grouped by cell, ascending
+    const uint4 *cells0;     // [K]      the cell record of bdoc[k] for k < K (repetition 0's grouping)
     uint64_t m;
     uint64_t K;
     uint32_t B, R, eta, RW;  // RW = 32-bit words per row (power of two)
@@ -746,10 +747,10 @@ __device__ __forceinline__ bool doc_kept(const Index &ix, const uint32_t *M, con
 }
 
 // Dense: every document tests its R cells; lane l handles document 64 w + l
-// and a ballot forms result word w. Four words' cell records are loaded
+// and a ballot forms result word w. Eight words' cell records are loaded
 // together.
 __device__ __forceinline__ uint64_t resolve_dense(const Index &ix, const uint32_t *M, uint64_t *out, uint32_t lane) {
-    constexpr uint32_t U = 4;
+    constexpr uint32_t U = 8;
     uint64_t pc = 0;  // this lane's documents kept
     for (uint32_t w0 = 0; w0 < ix.W; w0 += 64) {
         uint64_t mine = 0;
@@ -807,11 +808,15 @@ __device__ __forceinline__ uint64_t resolve_candidates(const Index &ix, const ui
         }
         const uint32_t total = __shfl(incl, 63);
         const uint32_t excl = incl - len;
-        for (uint32_t k0 = 0; k0 < total; k0 += 128) {
-            uint32_t pos[2];
-            bool has[2];
+        // a candidate's id and its cell record are loaded together (the
+        // records are also kept in repetition 0's grouping): one round trip
+        // per 64 * U candidates
+        constexpr int U = 4;
+        for (uint32_t k0 = 0; k0 < total; k0 += 64 * U) {
+            uint32_t pos[U];
+            bool has[U];
 #pragma unroll
-            for (int u = 0; u < 2; u++) {
+            for (int u = 0; u < U; u++) {
                 const uint32_t k = k0 + (uint32_t)u * 64 + lane;
                 has[u] = k < total;
                 // owner: the number of lanes whose inclusive sum is <= k (its
@@ -823,14 +828,15 @@ __device__ __forceinline__ uint64_t resolve_candidates(const Index &ix, const ui
                 const uint32_t ob = __shfl(beg, (int)lo), oe = __shfl(excl, (int)lo);
                 pos[u] = has[u] ? ob + (k - oe) : 0u;
             }
-            uint32_t d[2];
+            uint32_t d[U];
+            uint4 cd[U];
 #pragma unroll
-            for (int u = 0; u < 2; u++) d[u] = has[u] ? ix.bdoc[pos[u]] : 0u;
-            uint4 cd[2];
+            for (int u = 0; u < U; u++) {
+                d[u] = has[u] ? ix.bdoc[pos[u]] : 0u;
+                cd[u] = has[u] ? ix.cells0[pos[u]] : make_uint4(0u, 0u, 0u, 0u);
+            }
 #pragma unroll
-            for (int u = 0; u < 2; u++) cd[u] = has[u] ? ix.cells[d[u]] : make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-            for (int u = 0; u < 2; u++)
+            for (int u = 0; u < U; u++)
                 if (has[u] && doc_kept<1>(ix, M, cd[u]))
                     atomicOr((unsigned long long *)&res[d[u] >> 6], 1ULL << (d[u] & 63));
         }
@@ -892,11 +898,12 @@ __device__ __forceinline__ uint64_t resolve_candidates_out(const Index &ix, cons
                 pos[u] = has[u] ? ob + (k - oe) : 0u;
             }
             uint32_t d[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) d[u] = has[u] ? ix.bdoc[pos[u]] : 0u;
             uint4 cd[U];
 #pragma unroll
-            for (int u = 0; u < U; u++) cd[u] = has[u] ? ix.cells[d[u]] : make_uint4(0u, 0u, 0u, 0u);
+            for (int u = 0; u < U; u++) {
+                d[u] = has[u] ? ix.bdoc[pos[u]] : 0u;
+                cd[u] = has[u] ? ix.cells0[pos[u]] : make_uint4(0u, 0u, 0u, 0u);
+            }
 #pragma unroll
             for (int u = 0; u < U; u++)
                 if (has[u] && doc_kept<1>(ix, M, cd[u])) {

@@ -63,6 +63,7 @@ struct rambo_s {
     uint32_t *rows = nullptr;
     rambo::HashParams *d_hp = nullptr;
     uint4 *d_cells = nullptr;  // [K] phi_r(d) of every repetition, 16 bits each
+    uint4 *d_cells0 = nullptr; // [K] the same records in repetition 0's cell grouping (bdoc order)
     uint32_t *d_boff = nullptr, *d_bdoc = nullptr;
     unsigned long long *d_invalid = nullptr;  // [2]: invalid inputs, queries without a term
     unsigned long long *d_emptyq = nullptr;   // = d_invalid + 1
@@ -88,6 +89,7 @@ inline Index make_index(const rambo_s *h) {
     ix.cells = h->d_cells;
     ix.boff = h->d_boff;
     ix.bdoc = h->d_bdoc;
+    ix.cells0 = h->d_cells0;
     ix.m = h->m;
     ix.K = h->K;
     ix.B = h->B;
