@@ -292,11 +292,39 @@ def time_steps(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def host_cores():
+    """(threads the oracle may use, description of the host): every core this
+    process may run on (its affinity set), capped by OMP_NUM_THREADS when the
+    environment sets one (the share of the host granted to this job)."""
+    import platform
+    import subprocess
+    n = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit():
+        n = min(n, int(omp))
+    model = platform.processor()
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        nproc = None
+    return max(1, n), {"nproc": nproc, "os_cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+                       "omp_num_threads": omp, "model": model}
+
+
 def cpu_baseline(w, sample_reads, sample_docs, nthreads):
     """The oracle (Algorithm 2, early exit) on a bounded sample of the same
     workload: an index of the same shape (R, B, m, eta) holding documents
     0..sample_docs-1, queried with reads drawn from those documents with the
-    workload's length, error and random-read mix."""
+    workload's length, error and random-read mix. The sample's BFUs hold a
+    tenth of the workload's documents, so they are sparser and a Bloom test
+    fails sooner than on the full index: the rate is an upper bound of the
+    oracle's rate on the full workload."""
     import gen
     import oracle
     from dataclasses import replace
@@ -326,7 +354,8 @@ def cpu_baseline(w, sample_reads, sample_docs, nthreads):
     return {"value": kmers / q_s, "unit": "k-mer queries/s", "cores": nthreads, "kind": "oracle",
             "sample": "Algorithm 2 with early exit on %d reads (%d k-mers) drawn from documents 0..%d of the "
                       "workload (same length, error and random mix), against an oracle index of the "
-                      "workload's shape (R=%d, B=%d, m=2^%d, eta=%d) holding those %d documents; "
+                      "workload's shape (R=%d, B=%d, m=2^%d, eta=%d) holding those %d documents (a tenth of "
+                      "the workload's: sparser BFUs, so an upper bound of the oracle's rate on the full index); "
                       "query time %.2fs on %d threads (index build %.1fs not counted)"
                       % (sample_reads, kmers, sample_docs - 1, w.R, w.B, int(np.log2(w.m)), w.eta,
                          sample_docs, q_s, nthreads, build_s),
@@ -513,9 +542,10 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        nthr = max(1, min(16, os.cpu_count() or 1))
+        nthr, host = host_cores()
         cpu = cpu_baseline(w, args.cpu_reads, args.cpu_docs, nthr)
-        log("cpu oracle: %.3g k-mer/s on %d threads" % (cpu["value"], nthr))
+        cpu["host"] = host
+        log("cpu oracle: %.3g k-mer/s on %d threads (%s)" % (cpu["value"], nthr, host))
 
     served = None
     if not args.no_serve:

@@ -160,10 +160,45 @@ __global__ __launch_bounds__(256) void k_fold(const uint32_t *__restrict__ in, u
     }
 }
 
+// Rows of at most 128 bits (B <= 128): one thread per row, which loads the
+// row whole, folds it as one 128-bit value, v | (v >> B/2) on the low B/2
+// bits, and stores the folded row whole -- one load and one store per row,
+// coalesced across the wave.
+template <int RWI>
+__global__ __launch_bounds__(256) void k_fold_rows(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                   uint64_t rows, uint32_t RWo, uint32_t half) {
+    typedef unsigned __int128 u128;
+    const u128 keep = (((u128)1) << half) - 1;  // half <= 64
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t row = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; row < rows; row += stride) {
+        u128 v;
+        if constexpr (RWI == 4) {
+            const uint4 a = reinterpret_cast<const uint4 *>(in)[row];
+            v = (u128)a.x | ((u128)a.y << 32) | ((u128)a.z << 64) | ((u128)a.w << 96);
+        } else if constexpr (RWI == 2) {
+            const uint2 a = reinterpret_cast<const uint2 *>(in)[row];
+            v = (u128)a.x | ((u128)a.y << 32);
+        } else {
+            v = in[row];
+        }
+        const u128 f = (v | (v >> half)) & keep;
+        if (RWo == 2) {
+            reinterpret_cast<uint2 *>(out)[row] = make_uint2((uint32_t)f, (uint32_t)(f >> 32));
+        } else {
+            out[row] = (uint32_t)f;
+        }
+    }
+}
+
 int launch_fold(rambo_s *h, const uint32_t *in, uint32_t *out, uint32_t RWi, uint32_t log2RWo, uint32_t half,
                 hipStream_t s) {
     const uint64_t rows = (uint64_t)h->R * h->m;
-    hipLaunchKernelGGL(k_fold, dim3((unsigned)h->n_cu * 32), dim3(256), 0, s, in, out, rows, RWi, log2RWo, half);
+    const dim3 grid((unsigned)h->n_cu * 32), block(256);
+    const uint32_t RWo = 1u << log2RWo;  // (half <= 64 when RWi <= 4: RWo is 1 or 2)
+    if (RWi == 4) hipLaunchKernelGGL(k_fold_rows<4>, grid, block, 0, s, in, out, rows, RWo, half);
+    else if (RWi == 2) hipLaunchKernelGGL(k_fold_rows<2>, grid, block, 0, s, in, out, rows, RWo, half);
+    else if (RWi == 1) hipLaunchKernelGGL(k_fold_rows<1>, grid, block, 0, s, in, out, rows, RWo, half);
+    else hipLaunchKernelGGL(k_fold, grid, block, 0, s, in, out, rows, RWi, log2RWo, half);
     HIP_CHECK(hipGetLastError());
     return RAMBO_OK;
 }

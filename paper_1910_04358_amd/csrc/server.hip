@@ -72,6 +72,7 @@ struct rambo_server_s {
     std::mutex mu;  // pending queue, free slots, budget, stats
     std::condition_variable cv_dispatch, cv_done, cv_poll;
     std::deque<rambo::Request> pending;
+    std::atomic<uint64_t> n_pending{0};  // pending.size(), readable without the lock
     std::deque<int> free_slots, inflight;
     uint64_t budget_used = 0;
     bool stopping = false;
@@ -176,6 +177,11 @@ static void dispatcher_main(rambo_server_s *s) {
     for (;;) {
         int slot = -1;
         uint64_t n = 0, bytes = 0, cost = 0;
+        // an arrival is seen sooner by polling than by a wake-up: poll for up
+        // to 2 ms before sleeping on the condition variable (at rates above
+        // 500 reads/s the dispatcher never sleeps)
+        for (const double until = now_s() + 2e-3; s->n_pending.load(std::memory_order_acquire) == 0 && now_s() < until;)
+            std::this_thread::yield();
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_dispatch.wait(lk, [&] {
@@ -209,6 +215,7 @@ static void dispatcher_main(rambo_server_s *s) {
                 }
                 sl.reqs.push_back(r);
                 s->pending.pop_front();
+                s->n_pending.fetch_sub(1, std::memory_order_relaxed);
                 bytes += r.len;
                 cost += c;
                 n++;
@@ -314,6 +321,7 @@ static int enqueue_request(rambo_server_s *s, Request r) {
         }
         r.t_pending = now_s();
         s->pending.push_back(std::move(r));
+        s->n_pending.fetch_add(1, std::memory_order_release);
         s->stats.submitted++;
     }
     s->cv_dispatch.notify_one();
