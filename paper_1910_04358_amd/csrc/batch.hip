@@ -99,18 +99,26 @@ __host__ __device__ constexpr int scout_group(int G, bool narrow) {
 // Scout pass of the batched form (SCHED_SCOUT), before the queue is
 // built: repetition 0 on every read's scout windows (every 31st window and
 // the last, which together cover every base of the read). A group of GS
-// lanes takes one read, GS / G windows per round (G lanes split a row, as in
-// the main kernel), and ANDs the rounds' rows by lane exchanges. The AND is
-// stored in smask[i], the starting repetition-0 mask of the read's items, and
-// live[i] says whether it is non-empty. With early exit an empty AND ends the
-// read here (Section 3.3.1): its answer (a zero bitset, or a zero answer size
-// in id-list mode) is written now and the read never enters the queue. The
-// grid (up to 8 workgroups per CU, striding over the reads) keeps thousands
-// of reads in flight, which hides the latency of these few dependent steps; a
-// wave of the persistent kernel pays it in full, read by read. NARROW (id-list
-// mode, where an ended read costs no output) gives rows split over 8 or more
-// lanes 4 windows per round instead of 8: a finer early exit for fewer probes;
-// with bitsets the wider groups write the zero bitsets faster.
+// lanes takes one read at a time, GS / G windows per round (G lanes split a
+// row, as in the main kernel), and ANDs the rounds' rows by lane exchanges.
+// The AND is stored in smask[i], the starting repetition-0 mask of the read's
+// items, and live[i] says whether it is non-empty. With early exit an empty
+// AND ends the read here (Section 3.3.1): its answer (a zero bitset, or a
+// zero answer size in id-list mode) is written now and the read never enters
+// the queue.
+//
+// Most reads end after a round or two, so the pass is a chain of short
+// dependent steps (offsets, window bytes, rows) per read. Each group walks
+// its own reads (every stride-th one) independently of the other groups of
+// its wave -- a group whose read ended starts the next at once -- and loads
+// one round ahead: while a round's rows are in flight, the group also loads
+// the bytes of its read's next round and of its next read's first round, and
+// the offsets two reads ahead. A round then costs one memory round trip,
+// whichever way the read goes. The grid is what fits on the device at once.
+// NARROW (id-list mode, where an ended read costs no output) gives rows split
+// over 8 or more lanes 4 windows per round instead of 8: a finer early exit
+// for fewer probes; with bitsets the wider groups write the zero bitsets
+// faster.
 template <int SEG, int G, int NARROW>
 __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *in, uint64_t *__restrict__ out,
                                                      BatchBufs bb, QueryOpts opt) {
@@ -122,52 +130,102 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t sub = lane % GS, seg = sub % G, slot = sub / G;
     const uint64_t gmask = (GS >= 64) ? ~0ULL : (((1ULL << GS) - 1) << (lane - sub));  // the group's lanes
-    constexpr uint32_t GPB = 256 / GS;  // reads per workgroup and round of the grid
+    constexpr uint32_t GPB = 256 / GS;  // groups per workgroup
+    const uint64_t stride = (uint64_t)gridDim.x * GPB;
     __shared__ unsigned long long blk_issued;
     if (threadIdx.x == 0) blk_issued = 0;
     __syncthreads();
     uint64_t issued = 0;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * GPB; i0 < n; i0 += (uint64_t)gridDim.x * GPB) {
-        const uint64_t i = i0 + threadIdx.x / GS;
-        uint64_t beg = 0, end = 0;
-        if (i < n) {
-            beg = offs[i];
-            end = offs[i + 1];
-            if (end < beg) end = beg;
+
+    // the group's current read i, with the offsets of the next two at hand
+    uint64_t i = (uint64_t)blockIdx.x * GPB + threadIdx.x / GS;
+    // (offsets read as global memory, as the window bytes are: a generic
+    // load would also count against the scalar-load counter, and each wait
+    // for the hash parameters would wait for it; a read with end < beg has no
+    // window, which n_windows gives without clamping)
+    typedef const uint64_t __attribute__((address_space(1))) *goffs;
+    auto bounds = [&](uint64_t r, uint64_t &b, uint64_t &e) {
+        b = e = 0;
+        if (r < n) {
+            b = ((goffs)offs)[r];
+            e = ((goffs)offs)[r + 1];
         }
-        const uint64_t nw = n_windows(beg, end);
-        const uint64_t ns = nw ? scout_count(0, nw) : 0;
-        Seg<SEG> acc;
+    };
+    uint64_t beg, end, nbeg, nend, nnbeg = 0, nnend = 0;
+    bounds(i, beg, end);
+    bounds(i + stride, nbeg, nend);
+    bool need_offs = true;  // the offsets of read i + 2 stride are still to load
+    uint64_t nw = n_windows(beg, end), ns = nw ? scout_count(0, nw) : 0;
+    uint64_t k0 = 0;  // first scout window of the current round
+    WinBytes cur, next_round, next_read;
+    bool next_read_loaded = false;
+    if (i < n && slot < ns) load_window_bytes(cur, seqs + beg + scout_pos(0, nw, slot));
+    // repetition 0's hash functions (eta <= 2), held for the whole pass
+    const HashRec h0 = hash_rec(ix.hp->h, 0), h1 = hash_rec(ix.hp->h, ix.eta >= 2 ? 1 : 0);
+    Seg<SEG> acc;
 #pragma unroll
-        for (int s = 0; s < SEG; s++) acc.w[s] = 0xFFFFFFFFu;
-        bool live = true;   // uniform over the group
-        bool saw = false;   // some scout window was valid (uniform over the group)
-        for (uint64_t k0 = 0;; k0 += SLOTS) {
-            const bool active = live && k0 < ns;
-            if (__ballot(active) == 0) break;
-            Window wv;
-            wv.canon = 0;
-            wv.valid = false;
-            if (active && k0 + slot < ns) wv = window_at(seqs + beg + scout_pos(0, nw, k0 + slot));
-            Seg<SEG> cm[1];
+    for (int s = 0; s < SEG; s++) acc.w[s] = 0xFFFFFFFFu;
+    bool saw = false;  // some scout window of the read was valid (uniform over the group)
+    // Every load a round issues has completed when the round ends (explicit
+    // wait at its end): the loads ahead are issued first, then the round's
+    // rows, and the wait for the rows covers them all. The compiler's waits
+    // inside the loop then never hold a load ahead back.
+    __builtin_amdgcn_s_waitcnt(0);
+    for (;;) {
+        const bool have = i < n;
+        if (__ballot(have) == 0) break;
+        // loads ahead: the offsets two reads on, the bytes of this read's
+        // next round and of the next read's first round
+        const bool more = have && k0 + SLOTS < ns;
+        if (need_offs) {
+            bounds(i + 2 * stride, nnbeg, nnend);
+            need_offs = false;
+        }
+        if (more && k0 + SLOTS + slot < ns)
+            load_window_bytes(next_round, seqs + beg + scout_pos(0, nw, k0 + SLOTS + slot));
+        if (!next_read_loaded && i + stride < n) {
+            const uint64_t w2 = n_windows(nbeg, nend);
+            if (w2 && slot < scout_count(0, w2)) load_window_bytes(next_read, seqs + nbeg + scout_pos(0, w2, slot));
+            next_read_loaded = true;
+        }
+        // this round
+        Window wv;
+        wv.canon = 0;
+        wv.valid = false;
+        if (have && k0 + slot < ns) wv = decode_window(cur);
+        Seg<SEG> cm[1];
 #pragma unroll
-            for (int s = 0; s < SEG; s++) cm[0].w[s] = 0xFFFFFFFFu;
-            if (wv.valid) probe_reps<SEG, 0, 1>(ix, ix.hp->h, wv.canon, seg, cm);
-            const uint64_t vb = __ballot(wv.valid && seg == 0);
-            issued += (uint64_t)__popcll(vb);
-            saw |= (vb & gmask) != 0;
-            uint32_t o = 0;
+        for (int s = 0; s < SEG; s++) cm[0].w[s] = 0xFFFFFFFFu;
+        if (wv.valid) {
+            if (ix.eta <= 2) {
+                // both rows in flight together (with one hash function the
+                // same row twice)
+                const Seg<SEG> a = load_seg<SEG>(row_ptr(ix, 0, bloom_pos(h0, ix.m, wv.canon)) + seg * SEG);
+                const Seg<SEG> b = load_seg<SEG>(row_ptr(ix, 0, bloom_pos(h1, ix.m, wv.canon)) + seg * SEG);
 #pragma unroll
-            for (int s = 0; s < SEG; s++) {
-                uint32_t v = cm[0].w[s];
-#pragma unroll
-                for (int d = G; d < GS; d <<= 1) v &= (uint32_t)__shfl_xor((int)v, d);
-                acc.w[s] &= v;
-                o |= acc.w[s];
+                for (int s = 0; s < SEG; s++) cm[0].w[s] = a.w[s] & b.w[s];
+            } else {
+                probe_reps<SEG, 0, 1>(ix, ix.hp->h, wv.canon, seg, cm);
             }
-            if (opt.early_exit && (__ballot(o != 0) & gmask) == 0) live = false;
         }
-        if (i < n) {
+        const uint64_t vb = __ballot(wv.valid && seg == 0);
+        issued += (uint64_t)__popcll(vb);
+        saw |= (vb & gmask) != 0;
+        uint32_t o = 0;
+#pragma unroll
+        for (int s = 0; s < SEG; s++) {
+            uint32_t v = cm[0].w[s];
+#pragma unroll
+            for (int d = G; d < GS; d <<= 1) v &= (uint32_t)__shfl_xor((int)v, d);
+            acc.w[s] &= v;
+            o |= acc.w[s];
+        }
+        const bool live = !opt.early_exit || (__ballot(o != 0) & gmask) != 0;
+        if (have && live && more) {
+            k0 += SLOTS;
+            cur = next_round;
+        } else if (have) {
+            // read i is done: its scout AND, and the answer of an ended read
             if (slot == 0)
 #pragma unroll
                 for (int s = 0; s < SEG; s++) bb.smask[i * ix.RW + seg * SEG + s] = acc.w[s];
@@ -179,7 +237,23 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
                     for (uint32_t w = sub; w < ix.W; w += GS) out[i * ix.W + w] = 0;
                 }
             }
+            // on to the next read
+            i += stride;
+            beg = nbeg;
+            end = nend;
+            nbeg = nnbeg;
+            nend = nnend;
+            need_offs = true;
+            nw = n_windows(beg, end);
+            ns = nw ? scout_count(0, nw) : 0;
+            k0 = 0;
+            cur = next_read;
+            next_read_loaded = false;
+#pragma unroll
+            for (int s = 0; s < SEG; s++) acc.w[s] = 0xFFFFFFFFu;
+            saw = false;
         }
+        __builtin_amdgcn_s_waitcnt(0);
     }
     // one counter update per workgroup (same-address atomics serialise)
     if (opt.probes) {
@@ -358,10 +432,17 @@ static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
     if (pre) {
         const Index ix = make_index(h);
         const int G = (int)h->RW / tu.seg;
-        // a grid of at most 8 workgroups per CU strides over the reads
+        // a grid of what fits on the device at once strides over the reads
         const bool narrow = counts != nullptr;
         const uint64_t GS = (uint64_t)scout_group(G, narrow);
-        const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((bg.cap * GS + 255) / 256, 8ull * h->n_cu));
+        int fit = 0;
+#define RAMBO_SPLIT_BODY_                                                                                    \
+    HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                  \
+        &fit, narrow ? k_batch_scout<SEG, G, 1> : k_batch_scout<SEG, G, 0>, 256, 0))
+        RAMBO_DISPATCH_SPLIT(tu.seg, G)
+#undef RAMBO_SPLIT_BODY_
+        const uint64_t blocks = std::max<uint64_t>(
+            1, std::min<uint64_t>((bg.cap * GS + 255) / 256, (uint64_t)std::max(1, fit) * h->n_cu));
         QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, tu.sched, counts,
                       counts ? counts + bg.cap : h->d_emptyq};
 #define RAMBO_SPLIT_BODY_                                                                                   \

@@ -96,8 +96,24 @@ __device__ __forceinline__ uint64_t bloom_pos(const HashRec &p, uint64_t m, uint
     return __umul64hi(hi, m);
 }
 
+// Hash function i of the table at hp, read through the constant address
+// space: the table does not change while a kernel runs, so the loads are
+// scalar loads whatever the kernel stores (through a generic pointer, a
+// kernel that also stores to global memory gets vector loads, and each
+// would wait for the row loads issued before it).
+__device__ __forceinline__ HashRec hash_rec(const HashRec *hp, uint32_t i) {
+    typedef const HashRec __attribute__((address_space(4))) *ConstHash;
+    const ConstHash c = (ConstHash)hp + i;
+    HashRec r;
+    r.alo = c->alo;
+    r.ahi = c->ahi;
+    r.clo = c->clo;
+    r.chi = c->chi;
+    return r;
+}
+
 __device__ __forceinline__ uint64_t bloom_pos(const Index &ix, uint32_t i, uint64_t x) {
-    return bloom_pos(ix.hp->h[i], ix.m, x);
+    return bloom_pos(hash_rec(ix.hp->h, i), ix.m, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,7 +289,7 @@ __device__ __forceinline__ void probe_reps_eta(const Index &ix, const HashRec *h
         if (FIRST + k < (int)ix.R) {
 #pragma unroll
             for (int j = 0; j < ETA; j++) {
-                const uint64_t pos = bloom_pos(hp[(FIRST + k) * ETA + j], ix.m, x);
+                const uint64_t pos = bloom_pos(hash_rec(hp, (FIRST + k) * ETA + j), ix.m, x);
                 v[k][j] = load_seg<SEG>(row_ptr(ix, FIRST + k, pos) + seg * SEG);
             }
         }
@@ -296,7 +312,7 @@ __device__ __forceinline__ void probe_reps_any(const Index &ix, const HashRec *h
         if (FIRST + k < (int)ix.R) {
 #pragma unroll 1
             for (int j = 0; j < (int)ix.eta; j++) {
-                const uint64_t pos = bloom_pos(hp[(FIRST + k) * ix.eta + j], ix.m, x);
+                const uint64_t pos = bloom_pos(hash_rec(hp, (FIRST + k) * ix.eta + j), ix.m, x);
                 const Seg<SEG> v = load_seg<SEG>(row_ptr(ix, FIRST + k, pos) + seg * SEG);
 #pragma unroll
                 for (int s = 0; s < SEG; s++) cm[OFF + k].w[s] &= v.w[s];
@@ -328,7 +344,7 @@ __device__ __forceinline__ void probe_terms_eta(const Index &ix, const HashRec *
     for (int u = 0; u < U; u++)
 #pragma unroll
         for (int j = 0; j < ETA; j++) {
-            const uint64_t pos = v[u] ? bloom_pos(hp[r * ETA + j], ix.m, x[u]) : 0;
+            const uint64_t pos = v[u] ? bloom_pos(hash_rec(hp, r * ETA + j), ix.m, x[u]) : 0;
             rows[u][j] = load_seg<SEG>(row_ptr(ix, r, pos) + seg * SEG);
         }
 #pragma unroll
@@ -419,7 +435,9 @@ __device__ __forceinline__ bool probe_group(const Index &ix, const HashRec *hp, 
         // sub-steps per step)
         constexpr int KPW = 64 / G;
         constexpr int U = (G >= 4) ? 4 : G;  // sub-steps whose loads go together
-        if (COUNT == 1 && (ix.eta == 1 || ix.eta == 2)) {
+        // (a group of which only repetition FIRST is below R, e.g. the last
+        // one of R = 6, probes as a group of one)
+        if ((COUNT == 1 || (int)ix.R == FIRST + 1) && (ix.eta == 1 || ix.eta == 2)) {
             // one repetition, the rows of U sub-steps in flight together
 #pragma unroll 1
             for (int s0 = 0; s0 < G; s0 += U) {
@@ -581,6 +599,45 @@ __device__ __forceinline__ void stage_bytes(const uint8_t *__restrict__ seqs, ui
                 if (a + i >= first && a + i < last) dst[i] = a[i];
         }
     }
+}
+
+// The 31 bytes of a window held in registers, loaded ahead of their use:
+// bytes 0-15 in a, 16-27 in b, 28-29 in c and 30 in d, each part loaded by
+// one instruction and left as loaded (so that nothing waits for the loads
+// before the bytes are decoded). The bytes are read as global memory (a
+// generic access would also count against the wave's LDS and scalar-load
+// counter, and every wait for those would wait for these loads too).
+struct WinBytes {
+    uint4 a;
+    uint3 b;
+    uint32_t c, d;
+};
+__device__ __forceinline__ void load_window_bytes(WinBytes &wb, const uint8_t *p) {
+    typedef const uint8_t __attribute__((address_space(1))) *gbytes;
+    const gbytes g = (gbytes)p;
+    __builtin_memcpy(&wb.a, g, 16);
+    __builtin_memcpy(&wb.b, g + 16, 12);
+    uint16_t c;
+    __builtin_memcpy(&c, g + 28, 2);
+    wb.c = c;
+    wb.d = g[30];
+}
+
+// The window held in wb, encoded and made canonical.
+__device__ __forceinline__ Window decode_window(const WinBytes &wb) {
+    const uint32_t v[8] = {wb.a.x, wb.a.y, wb.a.z, wb.a.w, wb.b.x, wb.b.y, wb.b.z, wb.c | (wb.d << 16)};
+    uint64_t x = 0;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 31; i++) {
+        const uint32_t c = (v[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+        ok = ok && base_ok(c);
+        x = (x << 2) | base_code(c);
+    }
+    Window w;
+    w.valid = ok;
+    w.canon = canonical(x & MASK62);
+    return w;
 }
 
 // The window of 31 bytes at p (LDS), encoded and made canonical.
