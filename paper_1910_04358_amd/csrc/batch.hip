@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <type_traits>
 
 #include "batch.h"
 #include "scan.h"
@@ -157,9 +158,21 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
     bool need_offs = true;  // the offsets of read i + 2 stride are still to load
     uint64_t nw = n_windows(beg, end), ns = nw ? scout_count(0, nw) : 0;
     uint64_t k0 = 0;  // first scout window of the current round
-    WinBytes cur, next_round, next_read;
+    // A window's bytes are loaded and decoded by the P lanes that split its
+    // rows (P = 1: each lane takes a whole window).
+    constexpr int P = G >= 8 ? 8 : G;
+    using Bytes = std::conditional_t<(P > 1), WinPart<P>, WinBytes>;
+    auto load_win = [&](Bytes &b, const uint8_t *p) {
+        if constexpr (P > 1) load_window_part<P>(b, p, seg % P);
+        else load_window_bytes(b, p);
+    };
+    auto decode_win = [&](const Bytes &b) -> Window {
+        if constexpr (P > 1) return decode_window_parts<P>(b, seg % P);
+        else return decode_window(b);
+    };
+    Bytes cur{}, next_round{}, next_read{};
     bool next_read_loaded = false;
-    if (i < n && slot < ns) load_window_bytes(cur, seqs + beg + scout_pos(0, nw, slot));
+    if (i < n && slot < ns) load_win(cur, seqs + beg + scout_pos(0, nw, slot));
     // repetition 0's hash functions (eta <= 2), held for the whole pass
     const HashRec h0 = hash_rec(ix.hp->h, 0), h1 = hash_rec(ix.hp->h, ix.eta >= 2 ? 1 : 0);
     Seg<SEG> acc;
@@ -181,18 +194,15 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
             bounds(i + 2 * stride, nnbeg, nnend);
             need_offs = false;
         }
-        if (more && k0 + SLOTS + slot < ns)
-            load_window_bytes(next_round, seqs + beg + scout_pos(0, nw, k0 + SLOTS + slot));
+        if (more && k0 + SLOTS + slot < ns) load_win(next_round, seqs + beg + scout_pos(0, nw, k0 + SLOTS + slot));
         if (!next_read_loaded && i + stride < n) {
             const uint64_t w2 = n_windows(nbeg, nend);
-            if (w2 && slot < scout_count(0, w2)) load_window_bytes(next_read, seqs + nbeg + scout_pos(0, w2, slot));
+            if (w2 && slot < scout_count(0, w2)) load_win(next_read, seqs + nbeg + scout_pos(0, w2, slot));
             next_read_loaded = true;
         }
-        // this round
-        Window wv;
-        wv.canon = 0;
-        wv.valid = false;
-        if (have && k0 + slot < ns) wv = decode_window(cur);
+        // this round (every lane decodes: the lanes of a window exchange parts)
+        Window wv = decode_win(cur);
+        wv.valid = wv.valid && have && k0 + slot < ns;
         Seg<SEG> cm[1];
 #pragma unroll
         for (int s = 0; s < SEG; s++) cm[0].w[s] = 0xFFFFFFFFu;

@@ -640,6 +640,56 @@ __device__ __forceinline__ Window decode_window(const WinBytes &wb) {
     return w;
 }
 
+// A window's bytes split over P lanes (P = 2, 4 or 8, lanes q = 0 .. P-1 of
+// an aligned block): lane q holds window bytes qL .. qL+L-1 (L = 32 / P; the
+// last lane the L-1 bytes up to byte 30, loaded from one byte earlier so that
+// nothing past the window is read).
+template <int P>
+struct WinPart {
+    uint32_t w[32 / P / 4];
+};
+template <int P>
+__device__ __forceinline__ void load_window_part(WinPart<P> &wp, const uint8_t *p, uint32_t q) {
+    constexpr int L = 32 / P;
+    typedef const uint8_t __attribute__((address_space(1))) *gbytes;
+    const gbytes g = (gbytes)p + q * L - (q == P - 1 ? 1 : 0);
+    __builtin_memcpy(wp.w, g, L);
+}
+
+// The window whose parts the P lanes of each aligned block hold, encoded and
+// made canonical (every lane of the block gets it). Lane q encodes its bytes,
+// the block ORs the codes (invalid bytes flagged in bit 63) by lane exchanges.
+// Must be called by all 64 lanes.
+template <int P>
+__device__ __forceinline__ Window decode_window_parts(const WinPart<P> &wp, uint32_t q) {
+    constexpr int L = 32 / P, NW = L / 4;
+    const uint32_t last = q == P - 1 ? 1u : 0u;
+    // the last lane's bytes start one byte into its words
+    uint32_t v[NW];
+#pragma unroll
+    for (int k = 0; k < NW; k++)
+        v[k] = __builtin_amdgcn_alignbyte(k + 1 < NW ? wp.w[k + 1] : 0u, wp.w[k], last);
+    uint64_t y = 0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+        const uint32_t c = (v[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+        if (k < L - 1 || !last) {
+            bad |= !base_ok(c);
+            y = (y << 2) | base_code(c);
+        }
+    }
+    // bytes qL .. qL+n-1 (n = L - last) go to 4^(30 - j): shift the last one
+    // to 4^(30 - (qL + n - 1))
+    uint64_t part = (y << (2 * (31 - (q * L + L - last)))) | ((uint64_t)bad << 63);
+#pragma unroll
+    for (int d = 1; d < P; d <<= 1) part |= __shfl_xor(part, d);
+    Window w;
+    w.valid = (part >> 63) == 0;
+    w.canon = canonical(part & MASK62);
+    return w;
+}
+
 // The window of 31 bytes at p (LDS), encoded and made canonical.
 __device__ __forceinline__ Window window_at(const uint8_t *p) {
     uint64_t x = 0;
