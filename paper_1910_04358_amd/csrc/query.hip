@@ -355,35 +355,50 @@ int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *off
 // -------------------------------------------------------------------------
 // One wave per 64 reads: the reads with ids (a few per cent in id-list
 // workloads) are found with one ballot and compacted one after the other by
-// the whole wave; empty answers cost nothing more.
+// the whole wave; empty answers cost nothing more. A row is read 64 words at
+// a time (one coalesced load), eight such loads in flight together; each
+// 64-word chunk is placed by a prefix sum of its words' id counts. The total
+// (off[n]) is checked here: over cap, nothing is written and the host reports
+// the shortfall after the pass.
 __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ bits, uint64_t n, uint32_t W,
-                                                 const uint64_t *__restrict__ off, uint32_t *__restrict__ ids) {
+                                                 const uint64_t *__restrict__ off, uint32_t *__restrict__ ids,
+                                                 uint64_t cap) {
+    constexpr uint32_t U = 8;  // chunks in flight
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t i0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
-    if (i0 >= n) return;
+    if (i0 >= n || off[n] > cap) return;
     const uint64_t mine = i0 + lane;
     uint64_t todo = __ballot(mine < n && off[mine + 1] != off[mine]);
     while (todo) {
         const uint64_t i = i0 + (uint64_t)__builtin_ctzll(todo);
         todo &= todo - 1;
+        const uint64_t *row = bits + i * W;
         uint64_t base = off[i];
-        for (uint32_t w0 = 0; w0 < W; w0 += 64) {
-            const uint32_t w = w0 + lane;
-            uint64_t word = w < W ? bits[i * W + w] : 0;
-            const uint32_t pc = __popcll(word);
-            uint32_t incl = pc;
+        for (uint32_t c0 = 0; c0 < W; c0 += 64 * U) {
+            uint64_t word[U];
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t v = __shfl_up(incl, d);
-                if ((int)lane >= d) incl += v;
+            for (uint32_t u = 0; u < U; u++) {
+                const uint32_t w = c0 + 64 * u + lane;
+                word[u] = w < W ? row[w] : 0;
             }
-            uint64_t pos = base + incl - pc;
-            while (word) {
-                const uint32_t b = (uint32_t)__builtin_ctzll(word);
-                word &= word - 1;
-                ids[pos++] = w * 64 + b;
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++) {
+                const uint32_t w = c0 + 64 * u + lane;
+                const uint32_t pc = (uint32_t)__popcll(word[u]);
+                uint32_t incl = pc;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t v = __shfl_up(incl, d);
+                    if ((int)lane >= d) incl += v;
+                }
+                uint64_t pos = base + incl - pc;
+                uint64_t x = word[u];
+                while (x) {
+                    ids[pos++] = w * 64 + (uint32_t)__builtin_ctzll(x);
+                    x &= x - 1;
+                }
+                base += __shfl(incl, 63);
             }
-            base += __shfl(incl, 63);
         }
     }
 }
@@ -408,6 +423,14 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
     HIP_CHECK(hipGetLastError());
     int sst = launch_exclusive_scan(reinterpret_cast<const uint64_t *>(counts), d_n, n, id_off, parts, s);
     if (sst != RAMBO_OK) return sst;
+    // the compaction checks the total against ids_cap itself: no round trip
+    // to the host before it
+    if (ids) {
+        const uint64_t waves = (n + 63) / 64;
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, bits, n, W, id_off, ids,
+                           ids_cap);
+        HIP_CHECK(hipGetLastError());
+    }
     unsigned long long noterm = 0;
     hipError_t e = hipMemcpyAsync(&total, id_off + n, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && counts) e = hipMemcpyAsync(&noterm, counts + n, 8, hipMemcpyDeviceToHost, s);
@@ -416,13 +439,7 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
     if (total > ids_cap)
         return fail(RAMBO_ETRUNC, "rambo_query_seqs_ids: %llu ids do not fit %llu", (unsigned long long)total,
                     (unsigned long long)ids_cap);
-    if (total > 0) {
-        if (!ids) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null ids");
-        const uint64_t waves = (n + 63) / 64;
-        hipLaunchKernelGGL(k_compact, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, bits, n, W, id_off, ids);
-        HIP_CHECK(hipGetLastError());
-    }
-    HIP_CHECK(hipStreamSynchronize(s));
+    if (total > 0 && !ids) return fail(RAMBO_EINVAL, "rambo_query_seqs_ids: null ids");
     return noterm ? RAMBO_OK_EMPTYQ : RAMBO_OK;
 }
 
