@@ -63,7 +63,8 @@ def _serve(idx, reads, arrivals, policy, budget, slots=4, max_batch_reads=8192, 
     }, bits
 
 
-def run(idx, w, dev, log, rates=RATES, seconds=2.0, min_reads=2000, max_reads=100_000, budget=4 << 30):
+def run(idx, w, dev, log, rates=RATES, seconds=2.0, min_reads=2000, max_reads=100_000, budget=4 << 30,
+        verbose=False):
     import gen
     from paper_1910_04358_amd import MODE_PLAIN, SERVE_CONTINUOUS, SERVE_SERIAL
     import torch
@@ -91,6 +92,8 @@ def run(idx, w, dev, log, rates=RATES, seconds=2.0, min_reads=2000, max_reads=10
             if not np.array_equal(bits, ref):
                 raise SystemExit("served results differ from the plain kernel at rate %d (%s)" % (lam, name))
             rec[name] = m
+            if verbose:
+                log("serve %7d reads/s: %s done (p50 %.3f p99 %.3f ms)" % (lam, name, m["p50_ms"], m["p99_ms"]))
         log("serve %7d reads/s (%d reads): " % (lam, n) + " | ".join(
             "%s p50 %.3f p99 %.3f ms (wait %.3f/%.3f, service %.3f/%.3f; %.3g reads/s)"
             % (name, m["p50_ms"], m["p99_ms"], m["wait_p50_ms"], m["wait_p99_ms"], m["service_p50_ms"],
@@ -125,7 +128,7 @@ def main():
     w = gen.workload(4)
     idx, _, _ = bench.build_index(w, dev)
     rates = [int(r) for r in a.rates.split(",")]
-    out = run(idx, w, dev, log, rates=rates, seconds=1e9, min_reads=a.reads, max_reads=a.reads)
+    out = run(idx, w, dev, log, rates=rates, seconds=1e9, min_reads=a.reads, max_reads=a.reads, verbose=True)
     out["reads_per_rate"] = a.reads
     print(json.dumps({"workload": w.name, "served": out}), flush=True)
     idx.close()
