@@ -289,7 +289,9 @@ int rambo_fold(rambo_t *h);
 int rambo_query_kmers(rambo_t *h, const uint64_t *kmers, uint64_t n, uint64_t *out, void *stream);
 
 /* n sequence queries: read i is seqs[offsets[i] .. offsets[i+1]) (device
- * arrays; offsets non-decreasing). out (device, n * W words) receives, per
+ * arrays; offsets non-decreasing; a read holds fewer than 2^32 bytes, the
+ * kernels' window arithmetic within a read being 32-bit). out (device,
+ * n * W words) receives, per
  * read, the documents that hold every term of the read. A read with no valid
  * window gets every document (the vacuous "every term is in the BFU" of
  * Algorithm 2) and is counted for rambo_sync (RAMBO_OK_EMPTYQ). Once the

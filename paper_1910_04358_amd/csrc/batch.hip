@@ -97,6 +97,17 @@ __host__ __device__ constexpr int scout_group(int G, bool narrow) {
     return (narrow && G >= 8) ? (4 * G < 64 ? 4 * G : 64) : (16 * G < 64 ? 16 * G : 64);
 }
 
+// The scout pass's window arithmetic within one read (a read holds fewer
+// than 2^32 bytes): windows, scout windows and scout positions as in
+// n_windows, scout_count and scout_pos over the whole read, in 32 bits.
+__device__ __forceinline__ uint32_t windows32(uint64_t beg, uint64_t end) {
+    return end >= beg + 31 ? (uint32_t)(end - beg - 30) : 0u;
+}
+__device__ __forceinline__ uint32_t scout_count32(uint32_t nw) {
+    return nw ? (nw + 30) / 31 + ((nw - 1) % 31 != 0 ? 1u : 0u) : 0u;
+}
+__device__ __forceinline__ uint32_t scout_pos32(uint32_t nw, uint32_t k) { return min(31u * k, nw - 1); }
+
 // Scout pass of the batched form (SCHED_SCOUT), before the queue is
 // built: repetition 0 on every read's scout windows (every 31st window and
 // the last, which together cover every base of the read). A group of GS
@@ -156,8 +167,8 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
     bounds(i, beg, end);
     bounds(i + stride, nbeg, nend);
     bool need_offs = true;  // the offsets of read i + 2 stride are still to load
-    uint64_t nw = n_windows(beg, end), ns = nw ? scout_count(0, nw) : 0;
-    uint64_t k0 = 0;  // first scout window of the current round
+    uint32_t nw = windows32(beg, end), ns = scout_count32(nw);
+    uint32_t k0 = 0;  // first scout window of the current round
     // A window's bytes are loaded and decoded by the P lanes that split its
     // rows (P = 1: each lane takes a whole window).
     constexpr int P = G >= 8 ? 8 : G;
@@ -172,7 +183,7 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
     };
     Bytes cur{}, next_round{}, next_read{};
     bool next_read_loaded = false;
-    if (i < n && slot < ns) load_win(cur, seqs + beg + scout_pos(0, nw, slot));
+    if (i < n && slot < ns) load_win(cur, seqs + beg + scout_pos32(nw, slot));
     // repetition 0's hash functions (eta <= 2), held for the whole pass
     const HashRec h0 = hash_rec(ix.hp->h, 0), h1 = hash_rec(ix.hp->h, ix.eta >= 2 ? 1 : 0);
     Seg<SEG> acc;
@@ -194,10 +205,10 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
             bounds(i + 2 * stride, nnbeg, nnend);
             need_offs = false;
         }
-        if (more && k0 + SLOTS + slot < ns) load_win(next_round, seqs + beg + scout_pos(0, nw, k0 + SLOTS + slot));
+        if (more && k0 + SLOTS + slot < ns) load_win(next_round, seqs + beg + scout_pos32(nw, k0 + SLOTS + slot));
         if (!next_read_loaded && i + stride < n) {
-            const uint64_t w2 = n_windows(nbeg, nend);
-            if (w2 && slot < scout_count(0, w2)) load_win(next_read, seqs + nbeg + scout_pos(0, w2, slot));
+            const uint32_t w2 = windows32(nbeg, nend);
+            if (slot < scout_count32(w2)) load_win(next_read, seqs + nbeg + scout_pos32(w2, slot));
             next_read_loaded = true;
         }
         // this round (every lane decodes: the lanes of a window exchange parts)
@@ -254,8 +265,8 @@ __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *i
             nbeg = nnbeg;
             nend = nnend;
             need_offs = true;
-            nw = n_windows(beg, end);
-            ns = nw ? scout_count(0, nw) : 0;
+            nw = windows32(beg, end);
+            ns = scout_count32(nw);
             k0 = 0;
             cur = next_read;
             next_read_loaded = false;
