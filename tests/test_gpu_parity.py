@@ -171,35 +171,93 @@ def test_zero_false_negatives_and_strand_invariance():
     assert np.array_equal(got_rc, got)
 
 
-def test_edge_case_reads():
+@pytest.mark.parametrize("name", ["rw4", "rw32"])
+def test_edge_case_reads(name):
     """Empty, shorter than k, exactly k, all-invalid, invalid bytes inside,
-    lowercase, and a 10,000 bp read spanning many tiles."""
-    idx, o, dm, reads, want = setup_case("rw4")
+    lowercase, and a 10,000 bp read spanning many tiles; single windows with
+    one invalid or lowercase byte at every position where the lanes that
+    split a row also split the window's bytes (parts of 4, 8 and 16 bytes,
+    the last part loaded from one byte earlier). Every row split: seg 4, 2
+    and 1 words per lane (1, 2, 4 lanes per row at 4-word rows; 8, 16, 32 at
+    32-word rows)."""
+    idx, o, dm, reads, want = setup_case(name)
     d5 = dm.doc(5)
     cases = [b"", b"A", b"ACGT" * 7 + b"AC", d5[100:131], b"N" * 200, d5[0:200] + b"N" + d5[201:400],
              d5[1000:1300].lower(), d5[:10_000], b"ACGTX" * 40, d5[3000:3031] + b"\x00" + d5[3031:3100],
              d5[5000:5100]]
+    n_fixed = len(cases)
+    marks = (0, 1, 3, 4, 7, 8, 11, 12, 15, 16, 19, 20, 23, 24, 27, 28, 29, 30)
+    for k in marks:
+        w = bytearray(d5[2000 + 40 * k:2031 + 40 * k])
+        w[k] = ord("N")
+        cases.append(bytes(w))
+        w[k] = d5[2000 + 40 * k + k:2001 + 40 * k + k].lower()[0]
+        cases.append(bytes(w))
     seqs, offs = make_reads(cases)
     wantc = np.stack([o.query_seq(s) for s in cases])
     everyone = _ref.ids_to_bits(range(idx.K), idx.K)
-    for i in (0, 1, 2, 4, 8):
+    for i in [0, 1, 2, 4, 8] + list(range(n_fixed, len(cases), 2)):
         assert np.array_equal(wantc[i], everyone)
+    for i in range(n_fixed + 1, len(cases), 2):
+        assert (int(wantc[i][0]) >> 5) & 1  # a window of document 5, one base lowercased
     for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
         idx.set_mode(mode)
-        for sched in (0, 1, 2):
-            for tile in (64, 1024):
-                idx.set_tune(rb.Tune(4, tile, 8, 4, 1, sched))
-                got = to_host_u64(idx.query_seqs(to_dev(seqs), to_dev(offs)))
-                assert np.array_equal(got, wantc), (mode, sched, tile)
-                ids, id_off = idx.query_seqs_ids(to_dev(seqs), to_dev(offs), ids_cap=idx.K * len(cases))
-                ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
-                for i in range(len(cases)):
-                    assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(wantc[i], idx.K))
+        for seg, sched, tile in [(4, s, t) for s in (0, 1, 2) for t in (64, 1024)] + [(2, 2, 1024), (1, 2, 64)]:
+            idx.set_tune(rb.Tune(seg, tile, 8, 4, 1, sched))
+            got = to_host_u64(idx.query_seqs(to_dev(seqs), to_dev(offs)))
+            assert np.array_equal(got, wantc), (mode, seg, sched, tile)
+            ids, id_off = idx.query_seqs_ids(to_dev(seqs), to_dev(offs), ids_cap=idx.K * len(cases))
+            ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
+            for i in range(len(cases)):
+                assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(wantc[i], idx.K))
         # an empty batch
         e_seqs, e_offs = make_reads([])
         assert idx.query_seqs(to_dev(e_seqs), to_dev(e_offs)).shape[0] == 0
         ids, id_off = idx.query_seqs_ids(to_dev(e_seqs), to_dev(e_offs), ids_cap=0)
         assert ids.numel() == 0 and id_off.cpu().tolist() == [0]
+    idx.set_mode(rb.MODE_PLAIN)
+
+
+@pytest.mark.parametrize("name", ["rw4", "rw32"])
+def test_scout_pass_many_reads_per_lane_group(name):
+    """The batched form's scout pass gives each lane group every stride-th
+    read and loads a round ahead (the next round's window bytes, the next
+    read's first round, the offsets two reads on): with a batch of 80,000
+    short reads every group walks several reads, mixing reads that end in
+    the scout pass, reads that go on to the queue, reads without a window
+    (empty, shorter than 31, all N) and reads of exactly one window, at
+    random places. Bitsets and id lists against the oracle, read by read."""
+    idx, o, dm, reads, want = setup_case(name)
+    rng = np.random.default_rng(9090)
+    n = 80_000
+    lens = rng.integers(31, 160, n)
+    kinds = rng.integers(0, 10, n)
+    seqs = []
+    for i in range(n):
+        if kinds[i] == 0:
+            seqs.append([b"", b"ACGT", b"N" * 40, b"A" * 30][int(rng.integers(4))])
+            continue
+        d = int(rng.integers(dm.n_docs))
+        start = int(rng.integers(0, dm.length - int(lens[i])))
+        s = bytearray(dm.doc(d, start, int(lens[i])))
+        if kinds[i] <= 3:  # a substitution: mostly ends in the scout pass
+            j = int(rng.integers(len(s)))
+            s[j] = b"ACGT"[(b"ACGT".index(s[j]) + 1) % 4]
+        seqs.append(bytes(s))
+    hs, ho = make_reads(seqs)
+    wantn, _ = o.query_seqs(hs, ho, oracle.MODE_ALG2, early_exit=True)
+    assert (kinds >= 4).sum() > 40_000 and wantn.any(axis=1).sum() > 30_000
+    idx.set_mode(rb.MODE_BATCHED)
+    idx.set_tune(rb.Tune(4, 1024, 16, 4, 1, 2))
+    ds, do = to_dev(hs), to_dev(ho)
+    got = to_host_u64(idx.query_seqs(ds, do))
+    assert np.array_equal(got, wantn)
+    ids, id_off = idx.query_seqs_ids(ds, do, ids_cap=int(wantn.view(np.uint8).size * 8))
+    ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
+    for i in range(0, n, 7):
+        assert ids[id_off[i]:id_off[i + 1]].tolist() == sorted(_ref.bits_to_ids(wantn[i], idx.K)), i
+    counts = np.diff(id_off.astype(np.int64))
+    assert np.array_equal(counts, np.unpackbits(wantn.view(np.uint8), axis=1).sum(axis=1))
     idx.set_mode(rb.MODE_PLAIN)
 
 
