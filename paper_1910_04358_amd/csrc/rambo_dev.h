@@ -237,14 +237,26 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, uint32_t lane) 
 
 // AND across the k-mer groups of a wave: lanes l and l ^ off (off >= G) hold
 // the same row segment of different terms.
+// With one lane per term (G = 1) the AND of all 64 lanes, by lane moves
+// inside each row of 16 (DPP: lane ^ 1, lane ^ 2, the mirrored half-row, the
+// mirrored row) and the four rows' lanes read into scalar registers: no LDS
+// round trips in the chain, and the result (the same for every lane) kept
+// in a scalar register frees vector registers for loads in flight. Must be
+// called by all 64 lanes.
 template <int G>
 __device__ __forceinline__ uint32_t and_across_groups(uint32_t v) {
+    if constexpr (G == 1) {
+        v &= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        v &= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        v &= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        v &= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+        return __builtin_amdgcn_readlane(v, 0) & __builtin_amdgcn_readlane(v, 16) & __builtin_amdgcn_readlane(v, 32) &
+               __builtin_amdgcn_readlane(v, 48);
+    } else {
 #pragma unroll
-    for (int off = G; off < 64; off <<= 1) v &= __shfl_xor(v, off);
-    // one lane per term: the result is the same in every lane; keeping it in
-    // a scalar register frees vector registers for loads in flight
-    if constexpr (G == 1) v = __builtin_amdgcn_readfirstlane(v);
-    return v;
+        for (int off = G; off < 64; off <<= 1) v &= __shfl_xor(v, off);
+        return v;
+    }
 }
 
 template <int SEG, int G>
