@@ -786,7 +786,39 @@ __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t
         }
     }
     if ((sched == SCHED_SWEEP || skip0) && ix.R > 1) {
-        {
+        if (G == 1 && ix.eta <= 2) {
+            // one lane per term: repetition 0 over U0 steps at a time, their
+            // rows in flight together (a lane holds U0 terms), the next
+            // group's bytes loaded meanwhile
+            constexpr int U0 = 4;
+            StepBytes nb[U0];
+#pragma unroll
+            for (int u = 0; u < U0; u++) nb[u] = load_bytes(seqs, beg, end, w_lo + 64 * u, lane);
+            for (uint64_t w = w_lo; w < w_hi; w += 64 * U0) {
+                uint64_t xs[U0];
+                bool vs[U0];
+                uint64_t nv = 0;
+#pragma unroll
+                for (int u = 0; u < U0; u++) {
+                    const uint64_t wu = w + 64 * u;
+                    const Window wv = extract_windows(nb[u].c0, nb[u].c1, lane);
+                    vs[u] = wv.valid && (wu + lane < w_hi) && !(skip0 && is_scout(sk_lo, sk_hi, wu + lane));
+                    xs[u] = wv.canon;
+                    nv += (uint64_t)__popcll(__ballot(vs[u]));
+                }
+                if (w + 64 * U0 < w_hi)
+#pragma unroll
+                    for (int u = 0; u < U0; u++) nb[u] = load_bytes(seqs, beg, end, w + 64 * (U0 + u), lane);
+                Seg<SEG> cm;
+#pragma unroll
+                for (int t = 0; t < SEG; t++) cm.w[t] = 0xFFFFFFFFu;
+                if (ix.eta == 2) probe_terms_eta<SEG, U0, 2>(ix, step_params(ix), 0, xs, vs, 0, cm);
+                else probe_terms_eta<SEG, U0, 1>(ix, step_params(ix), 0, xs, vs, 0, cm);
+                const bool alive = fold_rep<SEG, G>(cm, M, lane);
+                issued += nv;
+                if (early_exit && !alive) return issued;
+            }
+        } else {
             StepBytes next = load_bytes(seqs, beg, end, w_lo, lane);
             for (uint64_t w = w_lo; w < w_hi; w += 64) {
                 const StepBytes cur = next;
