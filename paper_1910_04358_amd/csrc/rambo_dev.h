@@ -613,6 +613,19 @@ __device__ __forceinline__ void stage_bytes(const uint8_t *__restrict__ seqs, ui
     }
 }
 
+// Four bytes at a time (byte k of w in bits 8k..8k+7): the 2-bit code of
+// each byte (base_code, in the byte's low bits); which bytes are not a base
+// (non-zero bytes of the result: a byte is a base iff, made lowercase, it is
+// the letter its own code stands for, looked up by byte permute in "acgt");
+// and the four codes packed first-byte-most-significant into 8 bits (the
+// products of the multiply land in distinct bit ranges below bit 24, so no
+// carry reaches the top byte).
+__device__ __forceinline__ uint32_t codes4(uint32_t w) { return ((w >> 1) & 0x03030303u) ^ ((w >> 2) & 0x01010101u); }
+__device__ __forceinline__ uint32_t nonbases4(uint32_t w, uint32_t c) {
+    return (w | 0x20202020u) ^ __builtin_amdgcn_perm(0u, 0x74676361u, c);
+}
+__device__ __forceinline__ uint32_t pack4(uint32_t c) { return (c * 0x40100401u) >> 24; }
+
 // The 31 bytes of a window held in registers, loaded ahead of their use:
 // bytes 0-15 in a, 16-27 in b, 28-29 in c and 30 in d, each part loaded by
 // one instruction and left as loaded (so that nothing waits for the loads
@@ -635,20 +648,22 @@ __device__ __forceinline__ void load_window_bytes(WinBytes &wb, const uint8_t *p
     wb.d = g[30];
 }
 
-// The window held in wb, encoded and made canonical.
+// The window held in wb, encoded and made canonical, four bytes at a time:
+// 32 codes (the last from the zero byte past the window, dropped by the
+// final shift) and the non-bases of the 31 bytes.
 __device__ __forceinline__ Window decode_window(const WinBytes &wb) {
     const uint32_t v[8] = {wb.a.x, wb.a.y, wb.a.z, wb.a.w, wb.b.x, wb.b.y, wb.b.z, wb.c | (wb.d << 16)};
     uint64_t x = 0;
-    bool ok = true;
+    uint32_t bad = 0;
 #pragma unroll
-    for (int i = 0; i < 31; i++) {
-        const uint32_t c = (v[i >> 2] >> (8 * (i & 3))) & 0xFFu;
-        ok = ok && base_ok(c);
-        x = (x << 2) | base_code(c);
+    for (int k = 0; k < 8; k++) {
+        const uint32_t c = codes4(v[k]);
+        bad |= nonbases4(v[k], c) & (k == 7 ? 0x00FFFFFFu : 0xFFFFFFFFu);
+        x = (x << 8) | pack4(c);
     }
     Window w;
-    w.valid = ok;
-    w.canon = canonical(x & MASK62);
+    w.valid = bad == 0;
+    w.canon = canonical(x >> 2);
     return w;
 }
 
@@ -681,19 +696,19 @@ __device__ __forceinline__ Window decode_window_parts(const WinPart<P> &wp, uint
 #pragma unroll
     for (int k = 0; k < NW; k++)
         v[k] = __builtin_amdgcn_alignbyte(k + 1 < NW ? wp.w[k + 1] : 0u, wp.w[k], last);
+    // four bytes at a time; the last lane's top byte is past the window
     uint64_t y = 0;
-    bool bad = false;
+    uint32_t bad = 0;
 #pragma unroll
-    for (int k = 0; k < L; k++) {
-        const uint32_t c = (v[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-        if (k < L - 1 || !last) {
-            bad |= !base_ok(c);
-            y = (y << 2) | base_code(c);
-        }
+    for (int k = 0; k < NW; k++) {
+        const uint32_t c = codes4(v[k]);
+        bad |= nonbases4(v[k], c) & (k == NW - 1 && last ? 0x00FFFFFFu : 0xFFFFFFFFu);
+        y = (y << 8) | pack4(c);
     }
+    y >>= 2 * last;
     // bytes qL .. qL+n-1 (n = L - last) go to 4^(30 - j): shift the last one
     // to 4^(30 - (qL + n - 1))
-    uint64_t part = (y << (2 * (31 - (q * L + L - last)))) | ((uint64_t)bad << 63);
+    uint64_t part = (y << (2 * (31 - (q * L + L - last)))) | ((uint64_t)(bad != 0) << 63);
 #pragma unroll
     for (int d = 1; d < P; d <<= 1) part |= __shfl_xor(part, d);
     Window w;
