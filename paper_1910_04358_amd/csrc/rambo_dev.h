@@ -745,6 +745,77 @@ __device__ __forceinline__ StepBytes load_bytes(const uint8_t *__restrict__ seqs
     return {p < end ? (uint32_t)seqs[p] : 0u, (lane < 30 && p + 64 < end) ? (uint32_t)seqs[p + 64] : 0u};
 }
 
+// Repetitions 1..R-1 (R <= 5) of a work item's steps when a lane holds a
+// whole row (G = 1), two steps in flight: the rows of step w + 64 are issued
+// before those of step w are ANDed into the running masks, so a lane keeps up
+// to two steps' loads in flight (2 x 4 x ETA rows). The two row sets are
+// used alternately (no register copies, which would wait for the loads). A
+// step past the item issues its loads at row 0 of repetition 0 (in range,
+// unused). Returns the probes issued (with early exit, the step in flight
+// when the read ends counts too).
+template <int SEG, int ETA>
+__device__ __forceinline__ void issue_rows_g1(const Index &ix, const HashRec *hp, uint64_t x, bool valid,
+                                              Seg<SEG> (&r)[4][ETA]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int j = 0; j < ETA; j++) {
+            const bool use = valid && 1 + k < (int)ix.R;
+            const uint64_t pos = use ? bloom_pos(hash_rec(hp, (1 + k) * ETA + j), ix.m, x) : 0;
+            r[k][j] = load_seg<SEG>(row_ptr(ix, use ? 1 + k : 0, pos));
+        }
+}
+
+template <int SEG, int ETA>
+__device__ __forceinline__ uint64_t sweep_rest_g1(const Index &ix, const uint8_t *__restrict__ seqs, uint64_t beg,
+                                                  uint64_t end, uint64_t w_lo, uint64_t w_hi, uint32_t lane,
+                                                  uint32_t *M, bool early_exit) {
+    const uint32_t reps = ix.R - 1;
+    uint64_t issued = 0;
+    Seg<SEG> ra[4][ETA], rb[4][ETA];
+    bool va = false, vb = false;
+    StepBytes nb = load_bytes(seqs, beg, end, w_lo, lane);
+    // extract step w (its bytes in nb), load the next step's bytes, issue step w's rows
+    auto stage = [&](uint64_t w, Seg<SEG>(&r)[4][ETA], bool &v) {
+        const Window wv = extract_windows(nb.c0, nb.c1, lane);
+        v = wv.valid && (w + lane < w_hi);
+        nb = load_bytes(seqs, beg, end, w + 64, lane);
+        issue_rows_g1<SEG, ETA>(ix, step_params(ix), wv.canon, v, r);
+    };
+    // AND a step's rows into the running masks; false once one is empty
+    auto finish = [&](const Seg<SEG>(&r)[4][ETA], bool v) -> bool {
+        bool alive = true;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (1 + k < (int)ix.R) {
+                Seg<SEG> cm;
+#pragma unroll
+                for (int t = 0; t < SEG; t++) cm.w[t] = 0xFFFFFFFFu;
+                if (v)
+#pragma unroll
+                    for (int j = 0; j < ETA; j++)
+#pragma unroll
+                        for (int t = 0; t < SEG; t++) cm.w[t] &= r[k][j].w[t];
+                alive &= fold_rep<SEG, 1>(cm, M + (1 + k) * ix.RW, lane);
+            }
+        }
+        return alive;
+    };
+    stage(w_lo, ra, va);
+    for (uint64_t w = w_lo;;) {
+        stage(w + 64, rb, vb);
+        issued += (uint64_t)__popcll(__ballot(va)) * reps;
+        if (!finish(ra, va) && early_exit) return issued + (uint64_t)__popcll(__ballot(vb)) * reps;
+        w += 64;
+        if (w >= w_hi) return issued;
+        stage(w + 64, ra, va);
+        issued += (uint64_t)__popcll(__ballot(vb)) * reps;
+        if (!finish(rb, vb) && early_exit) return issued + (uint64_t)__popcll(__ballot(va)) * reps;
+        w += 64;
+        if (w >= w_hi) return issued;
+    }
+}
+
 // Probe windows [w_lo, w_hi) of the read held in seqs[beg, end) into the
 // running masks in M, 64 windows per step; the step's masks are ANDed across
 // the wave (G lanes share a term). With early exit the probing stops once a
@@ -844,6 +915,10 @@ __device__ __forceinline__ uint64_t probe_windows(const Index &ix, const uint8_t
                 issued += (uint64_t)__popcll(__ballot(valid));
                 if (early_exit && !alive) return issued;
             }
+        }
+        if constexpr (G == 1 && !RPLUS) {
+            if (ix.R <= 5 && ix.eta == 2) return issued + sweep_rest_g1<SEG, 2>(ix, seqs, beg, end, w_lo, w_hi, lane, M, early_exit);
+            if (ix.R <= 5 && ix.eta == 1) return issued + sweep_rest_g1<SEG, 1>(ix, seqs, beg, end, w_lo, w_hi, lane, M, early_exit);
         }
         StepBytes next = load_bytes(seqs, beg, end, w_lo, lane);
         for (uint64_t w = w_lo; w < w_hi; w += 64) {
