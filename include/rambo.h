@@ -441,9 +441,13 @@ typedef struct {
     uint32_t queue_cap;       /* pending reads before submit returns RAMBO_EBUSY */
     uint32_t direct_below;    /* continuous policy: batches of fewer reads launch
                                  the plain kernel directly instead of replaying
-                                 the slot's graph (0: always replay; 2049, the
-                                 Python binding's default, measured lowest
-                                 latency on MI355X at 1k-50k reads/s) */
+                                 a graph of the slot (0: always replay). Batches
+                                 of up to 64 reads are read in place from pinned
+                                 memory, larger ones through device copies; 65,
+                                 the Python binding's default, launches the
+                                 former directly (lowest latency at 1k-50k
+                                 reads/s on MI355X) and replays graphs for the
+                                 latter (higher throughput near saturation) */
     uint32_t batch_wait_us;   /* batching window: a batch smaller than
                                  max_batch_reads is held until its oldest read
                                  has been pending this long (0: never held,

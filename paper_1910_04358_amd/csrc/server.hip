@@ -6,11 +6,13 @@
 // (device bytes of the in-flight reads and their result state), copies it
 // on the slot's own stream; up to `slots` batches are in flight at once, so
 // the work of one batch overlaps that of another and reads that arrive while
-// others run join the next batch. Batches below direct_below reads are read
-// by the kernel straight from the slot's pinned staging area and answered
-// straight into its pinned result area (no copy operations: one launch per
-// batch); larger ones are copied to the device and replayed from the slot's
-// captured persistent-form graphs, their results copied back. A completion
+// others run join the next batch. Batches of up to 64 reads are read by the
+// kernel straight from the slot's pinned staging area and answered straight
+// into its pinned result area (no copy operations: one launch or one graph
+// replay per batch); larger ones are copied to the device, run there (the
+// plain kernel launched directly below direct_below reads, else the slot's
+// captured graphs: the plain kernel's up to 2,048 reads, the persistent
+// form's beyond) and their results copied back. A completion
 // thread takes each batch as soon as it is done (in any order), hands its
 // results over and stamps the completion time. Each result is the same
 // bitset rambo_query_seqs gives for that read alone: reads are independent
@@ -57,7 +59,9 @@ struct Slot {
     // the pinned staging and result areas as the device addresses them
     uint8_t *hd_stage = nullptr;
     uint64_t *hd_out = nullptr;
-    std::shared_ptr<BatchGraph> small, large;  // plain-kernel graph for small batches, persistent for large
+    // plain-kernel graphs for small batches (on the pinned areas, and on the
+    // device copy), the persistent form's for large ones
+    std::shared_ptr<BatchGraph> small, mid, large;
     std::vector<Request> reqs;
     uint64_t budget = 0;
     double t_admit = 0;
@@ -133,12 +137,19 @@ static uint64_t pack_slot(Slot &sl, const uint8_t *base) {
     return kHdrBytes + (n + 1) * 8 + off;
 }
 
+// Batches of at most this many reads are served from the pinned areas in
+// place: the kernel's byte loads and result stores then cross the host bus,
+// which for a few reads costs less than the two copies, and for hundreds of
+// reads (the batches of high arrival rates) far more.
+static constexpr uint64_t kZeroCopyMaxReads = 64;
+
 // Whether the continuous policy serves an n-read batch from the pinned areas
 // directly (the plain kernel launched directly, or the slot's plain-kernel
 // graph, both reading the pinned staging area and writing the pinned result
-// area) rather than through device copies and the persistent form.
+// area) rather than through device copies.
 static bool zero_copy(const rambo_server_s *s, const Slot &sl, uint64_t n) {
-    return s->cfg.policy == RAMBO_SERVE_CONTINUOUS && (n < s->cfg.direct_below || n <= sl.small->cap);
+    return s->cfg.policy == RAMBO_SERVE_CONTINUOUS && n <= kZeroCopyMaxReads &&
+           (n < s->cfg.direct_below || n <= sl.small->cap);
 }
 
 static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n) {
@@ -155,10 +166,12 @@ static int launch_slot(rambo_server_s *s, Slot &sl, uint64_t n) {
         st = launch_batch_graph(h, *sl.small, sl.stream);
     } else {
         HIP_CHECK(hipMemcpyAsync(sl.d_stage, sl.h_stage, copy_bytes, hipMemcpyHostToDevice, sl.stream));
-        if (s->cfg.policy == RAMBO_SERVE_SERIAL) {
+        if (s->cfg.policy == RAMBO_SERVE_SERIAL || n < s->cfg.direct_below) {
             const uint64_t *offs = (const uint64_t *)(sl.d_stage + kHdrBytes);
             st = launch_query_seqs_plain(h, sl.d_stage + kHdrBytes + (n + 1) * 8, offs, n, sl.d_out, sl.stream,
                                          default_seg(h->RW));
+        } else if (n <= sl.mid->cap) {
+            st = launch_batch_graph(h, *sl.mid, sl.stream);
         } else {
             st = launch_batch_graph(h, *sl.large, sl.stream);
         }
@@ -352,6 +365,7 @@ static void feeder_main(rambo_server_s *s) {
 
 static void free_slot(Slot &sl) {
     sl.small.reset();
+    sl.mid.reset();
     sl.large.reset();
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -379,8 +393,9 @@ static int setup_slot(rambo_server_s *s, Slot &sl) {
         // small batches: the plain kernel, one wave per read, on the pinned
         // areas; large ones: the persistent form with the handle's tuned
         // shape on the device copy
-        const uint64_t small_cap = std::min<uint64_t>(R, 2048);
+        const uint64_t small_cap = std::min<uint64_t>(R, kZeroCopyMaxReads), mid_cap = std::min<uint64_t>(R, 2048);
         int st = make_plain_graph(h, (const InputHdr *)sl.hd_stage, small_cap, sl.hd_out, sl.small);
+        if (st == RAMBO_OK) st = make_plain_graph(h, (const InputHdr *)sl.d_stage, mid_cap, sl.d_out, sl.mid);
         if (st == RAMBO_OK)
             st = make_batch_graph(h, large, (const InputHdr *)sl.d_stage, nullptr, R, sl.d_out, sl.large);
         if (st != RAMBO_OK) return st;
@@ -392,6 +407,7 @@ static int setup_slot(rambo_server_s *s, Slot &sl) {
         hdr->seqs = sl.hd_stage + kHdrBytes;
         HIP_CHECK(hipMemcpy(sl.d_stage, sl.h_stage, sizeof(InputHdr), hipMemcpyHostToDevice));
         if ((st = launch_batch_graph(h, *sl.small, sl.stream)) != RAMBO_OK) return st;
+        if ((st = launch_batch_graph(h, *sl.mid, sl.stream)) != RAMBO_OK) return st;
         if ((st = launch_batch_graph(h, *sl.large, sl.stream)) != RAMBO_OK) return st;
         HIP_CHECK(hipStreamSynchronize(sl.stream));
     }

@@ -463,7 +463,7 @@ class Server:
     """Continuous-batching server over a resident index (RAMBO_SERVE_*)."""
 
     def __init__(self, idx: "Rambo", budget_bytes=4 << 30, slots=4, max_batch_reads=8192,
-                 max_batch_bytes=8 << 20, policy=SERVE_CONTINUOUS, queue_cap=1 << 20, direct_below=2049,
+                 max_batch_bytes=8 << 20, policy=SERVE_CONTINUOUS, queue_cap=1 << 20, direct_below=65,
                  batch_wait_us=0):
         self.idx = idx
         cfg = ServerConfig(budget_bytes, slots, max_batch_reads, max_batch_bytes, policy, queue_cap, direct_below,

@@ -18,7 +18,7 @@ RATES = (1000, 5000, 10000, 25000, 50000)
 
 
 def _serve(idx, reads, arrivals, policy, budget, slots=4, max_batch_reads=8192, max_batch_bytes=8 << 20,
-           direct_below=2049):
+           direct_below=65):
     from paper_1910_04358_amd import Server, clock
 
     n = reads.n
@@ -82,11 +82,11 @@ def run(idx, w, dev, log, rates=RATES, seconds=2.0, min_reads=2000, max_reads=10
         offs = torch.from_numpy(reads.offsets.view(np.int64)).to(dev)
         ref = idx.query_seqs(seqs, offs).cpu().numpy().view(np.uint64)
         rec = {"rate": lam, "reads": n}
-        # served: continuous batching, batches of up to 2048 reads launched
-        # directly, larger ones replayed from the slot's persistent graph;
-        # served_graph: every batch replayed from a graph; serial_plain: the
-        # one-batch-at-a-time baseline
-        for name, policy, direct in (("served", SERVE_CONTINUOUS, 2049), ("served_graph", SERVE_CONTINUOUS, 0),
+        # served: continuous batching, batches of up to 64 reads launched
+        # directly on the pinned areas, larger ones copied and replayed from
+        # the slot's graphs; served_graph: every batch replayed from a graph;
+        # serial_plain: the one-batch-at-a-time baseline
+        for name, policy, direct in (("served", SERVE_CONTINUOUS, 65), ("served_graph", SERVE_CONTINUOUS, 0),
                                      ("serial_plain", SERVE_SERIAL, 0)):
             m, bits = _serve(idx, reads, arrivals, policy, budget, direct_below=direct)
             if not np.array_equal(bits, ref):

@@ -27,7 +27,7 @@ def collect(srv, n, timeout=30.0):
     return bits
 
 
-@pytest.mark.parametrize("policy,direct_below", [(rb.SERVE_CONTINUOUS, 2049), (rb.SERVE_CONTINUOUS, 0),
+@pytest.mark.parametrize("policy,direct_below", [(rb.SERVE_CONTINUOUS, 2049), (rb.SERVE_CONTINUOUS, 65), (rb.SERVE_CONTINUOUS, 0),
                                                  (rb.SERVE_SERIAL, 0)])
 def test_served_results_equal_oracle(policy, direct_below):
     """Batches launched directly (small), replayed from the slot's plain-kernel
@@ -67,6 +67,27 @@ def test_large_served_batches_use_the_persistent_form(direct_below):
         assert np.array_equal(bits[i], want[i]), i
     assert st["max_batch_reads"] > 2048, st
     assert st["batches"] <= 2, st
+
+
+@pytest.mark.parametrize("direct_below", [0, 2049])
+def test_medium_served_batches_through_device_copies(direct_below):
+    """Batches of more than 64 reads are copied to the device rather than
+    read in place from pinned memory: one batch of 500 reads (held by the
+    batching window until complete) runs the plain kernel on the device copy,
+    launched directly or replayed from the slot's plain-kernel graph; results
+    equal the oracle's."""
+    idx, o, dm, reads, want = setup_case("rw4")
+    n = 500
+    srv = rb.Server(idx, budget_bytes=1 << 30, slots=2, max_batch_reads=n, max_batch_bytes=64 << 20,
+                    direct_below=direct_below, batch_wait_us=200_000)
+    t0 = rb.clock() + 0.05
+    srv.submit_schedule(reads.seqs[: int(reads.offsets[n])], reads.offsets[: n + 1], np.full(n, t0))
+    bits = collect(srv, n)
+    st = srv.stats()
+    srv.stop()
+    for i in range(n):
+        assert np.array_equal(bits[i], want[i]), i
+    assert st["max_batch_reads"] == n and st["batches"] == 1, st
 
 
 def test_burst_alone_vs_mix_and_backpressure():
