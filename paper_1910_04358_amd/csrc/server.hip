@@ -80,7 +80,7 @@ struct rambo_server_s {
     std::deque<int> free_slots, inflight;
     uint64_t budget_used = 0;
     bool stopping = false;
-    int error = RAMBO_OK;
+    std::atomic<int> error{RAMBO_OK};  // written under mu, read under either lock
     std::string error_msg;
     std::thread dispatcher, completer, feeder;
     // completions
@@ -106,8 +106,10 @@ static uint64_t request_cost(const rambo_s *h, uint64_t len) {
 static void server_fail(rambo_server_s *s, int st) {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->error == RAMBO_OK) {
-        s->error = st;
+        // the message is written before the code: readers under the other
+        // lock look at the message only once they see the code set
         s->error_msg = rambo_last_error();
+        s->error = st;
     }
     s->stopping = true;
     s->cv_dispatch.notify_all();
@@ -293,18 +295,27 @@ static void completer_main(rambo_server_s *s) {
         }
         Slot &sl = s->slots[slot];
         const double t_done = now_s();
+        // the batch's completions and result copies are made before the
+        // lock is taken, and only moved in under it (a poller holding the
+        // lock must not stall this thread for long)
+        const size_t nr = sl.reqs.size();
+        std::vector<rambo_completion_t> cs(nr);
+        std::vector<std::vector<uint64_t>> bs(nr);
+        for (size_t i = 0; i < nr; i++) {
+            rambo_completion_t &c = cs[i];
+            c.tag = sl.reqs[i].tag;
+            c.t_arrival = sl.reqs[i].t_arrival;
+            c.t_admit = sl.t_admit;
+            c.t_done = t_done;
+            c.status = RAMBO_OK;
+            c.batch_reads = (uint32_t)nr;
+            bs[i].assign(sl.h_out + i * W, sl.h_out + (i + 1) * W);
+        }
         {
             std::lock_guard<std::mutex> g(s->cmu);
-            for (size_t i = 0; i < sl.reqs.size(); i++) {
-                rambo_completion_t c;
-                c.tag = sl.reqs[i].tag;
-                c.t_arrival = sl.reqs[i].t_arrival;
-                c.t_admit = sl.t_admit;
-                c.t_done = t_done;
-                c.status = RAMBO_OK;
-                c.batch_reads = (uint32_t)sl.reqs.size();
-                s->comp.push_back(c);
-                s->comp_bits.emplace_back(sl.h_out + i * W, sl.h_out + (i + 1) * W);
+            for (size_t i = 0; i < nr; i++) {
+                s->comp.push_back(cs[i]);
+                s->comp_bits.push_back(std::move(bs[i]));
             }
         }
         s->cv_poll.notify_all();
@@ -375,6 +386,28 @@ static void free_slot(Slot &sl) {
     if (sl.d_out) (void)hipFree(sl.d_out);
 }
 
+// The runtime sets up its copy engines on their first use, for several
+// milliseconds each during which the issuing call blocks, once per process;
+// which engine a copy takes depends on the copies already in flight. Copies
+// of every size class in both directions, in flight on all slots' streams at
+// once, meet those set-up costs here rather than in the middle of a burst.
+static int warm_copies(rambo_server_s *s) {
+    const uint64_t R = s->cfg.max_batch_reads, BY = s->cfg.max_batch_bytes;
+    const uint64_t stage = kHdrBytes + (R + 1) * 8 + BY, out_bytes = R * s->h->W * 8;
+    for (int rep = 0; rep < 2; rep++) {
+        for (uint64_t sz : {uint64_t(4) << 10, uint64_t(64) << 10, uint64_t(1) << 20, ~uint64_t(0)}) {
+            for (Slot &sl : s->slots) {
+                HIP_CHECK(hipMemcpyAsync(sl.d_stage, sl.h_stage, std::min(sz, stage), hipMemcpyHostToDevice,
+                                         sl.stream));
+                HIP_CHECK(hipMemcpyAsync(sl.h_out, sl.d_out, std::min(sz, out_bytes), hipMemcpyDeviceToHost,
+                                         sl.stream));
+            }
+        }
+        for (Slot &sl : s->slots) HIP_CHECK(hipStreamSynchronize(sl.stream));
+    }
+    return RAMBO_OK;
+}
+
 static int setup_slot(rambo_server_s *s, Slot &sl) {
     rambo_s *h = s->h;
     const uint64_t R = s->cfg.max_batch_reads, BY = s->cfg.max_batch_bytes;
@@ -441,6 +474,7 @@ RAMBO_API rambo_server_t *rambo_server_start(rambo_t *h, const rambo_server_conf
         st = setup_slot(s, s->slots[i]);
         s->free_slots.push_back((int)i);
     }
+    if (st == RAMBO_OK) st = warm_copies(s);
     if (st != RAMBO_OK) {
         for (auto &sl : s->slots) free_slot(sl);
         delete s;
@@ -478,19 +512,31 @@ RAMBO_API int rambo_server_poll(rambo_server_t *s, rambo_completion_t *out, uint
                                 double timeout_s) {
     if (!s || (!out && max)) return fail(RAMBO_EINVAL, "rambo_server_poll: bad argument");
     const uint64_t W = s->h->W;
-    std::unique_lock<std::mutex> lk(s->cmu);
-    if (s->comp.empty() && timeout_s > 0) {
-        s->cv_poll.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return !s->comp.empty() || s->error; });
-    }
+    // take the completions out under the lock (moves only) and copy them to
+    // the caller's arrays after it is released, so the completion thread,
+    // which needs the lock for every batch, is not held up by the copies
+    std::vector<std::vector<uint64_t>> bits;
     uint32_t k = 0;
-    while (k < max && !s->comp.empty()) {
-        out[k] = s->comp.front();
-        if (results) memcpy(results + (uint64_t)k * W, s->comp_bits.front().data(), W * 8);
-        s->comp.pop_front();
-        s->comp_bits.pop_front();
-        k++;
+    int err = RAMBO_OK;
+    {
+        std::unique_lock<std::mutex> lk(s->cmu);
+        if (s->comp.empty() && timeout_s > 0) {
+            s->cv_poll.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return !s->comp.empty() || s->error; });
+        }
+        const uint32_t take = (uint32_t)std::min<uint64_t>(max, s->comp.size());
+        bits.reserve(take);
+        while (k < take) {
+            out[k] = s->comp.front();
+            bits.push_back(std::move(s->comp_bits.front()));
+            s->comp.pop_front();
+            s->comp_bits.pop_front();
+            k++;
+        }
+        err = s->error;
     }
-    if (k == 0 && s->error != RAMBO_OK) return fail(s->error, "server failed: %s", s->error_msg.c_str());
+    if (results)
+        for (uint32_t i = 0; i < k; i++) memcpy(results + (uint64_t)i * W, bits[i].data(), W * 8);
+    if (k == 0 && err != RAMBO_OK) return fail(err, "server failed: %s", s->error_msg.c_str());
     return (int)k;
 }
 
