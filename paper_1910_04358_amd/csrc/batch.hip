@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t
 
 // lanes per read in the scout pass
 __host__ __device__ constexpr int scout_group(int G, bool narrow) {
-    return (narrow && G >= 8) ? (4 * G < 64 ? 4 * G : 64) : (16 * G < 64 ? 16 * G : 64);
+    return (narrow && G >= 8) ? G : (16 * G < 64 ? 16 * G : 64);
 }
 
 // The scout pass's window arithmetic within one read (a read holds fewer
@@ -128,9 +128,11 @@ __device__ __forceinline__ uint32_t scout_pos32(uint32_t nw, uint32_t k) { retur
 // the offsets two reads ahead. A round then costs one memory round trip,
 // whichever way the read goes. The grid is what fits on the device at once.
 // NARROW (id-list mode, where an ended read costs no output) gives rows split
-// over 8 or more lanes 4 windows per round instead of 8: a finer early exit
-// for fewer probes; with bitsets the wider groups write the zero bitsets
-// faster.
+// over 8 or more lanes one window per round (a group of G lanes per read)
+// instead of 8: the read ends at its first empty window, with no probes of
+// the windows after it, and a wave holds as many rows in flight as with wider
+// groups, as it walks 8 reads at once; with bitsets the wider groups write the
+// zero bitsets faster.
 template <int SEG, int G, int NARROW>
 __global__ __launch_bounds__(256) void k_batch_scout(Index ix, const InputHdr *in, uint64_t *__restrict__ out,
                                                      BatchBufs bb, QueryOpts opt) {
