@@ -35,19 +35,6 @@ static uint64_t splitmix_next(uint64_t &s) {
 
 static constexpr uint64_t P61 = (1ULL << 61) - 1;
 
-// The row array, physically contiguous where the device can give it: the
-// probes are uniformly random reads over the whole array, and contiguous
-// memory is mapped with larger translation fragments, so fewer of them miss
-// the GPU's address translation caches (measured: the batched pass over a
-// 40 GiB index about 6 % faster). Falls back to an ordinary allocation.
-static hipError_t alloc_rows(uint32_t **p, uint64_t bytes) {
-    *p = nullptr;
-    if (hipExtMallocWithFlags((void **)p, bytes, hipDeviceMallocContiguous) == hipSuccess && *p) return hipSuccess;
-    (void)hipGetLastError();
-    *p = nullptr;
-    return hipMalloc((void **)p, bytes);
-}
-
 // Draw the partition and Bloom hash parameters, then phi_r(d) for all d.
 static void derive_hashes(rambo_s *h) {
     uint64_t s = h->seed;
@@ -194,7 +181,7 @@ rambo_s *rambo::create_index(uint64_t K, uint32_t B, uint32_t R, uint64_t m, uin
         return nullptr;
     }
     derive_hashes(h);
-    if (alloc_rows(&h->rows, h->rows_bytes) != hipSuccess) {
+    if (hipMalloc(&h->rows, h->rows_bytes) != hipSuccess) {
         (void)hipGetLastError();
         fail(RAMBO_ENOMEM, "rambo_create: cannot allocate %llu bytes of index on the device",
              (unsigned long long)h->rows_bytes);
@@ -294,7 +281,7 @@ RAMBO_API int rambo_fold(rambo_t *h) {
     while (rw < need) { rw <<= 1; lg++; }
     const uint64_t bytes = (uint64_t)h->R * h->m * rw * 4;
     uint32_t *nrows = nullptr;
-    if (alloc_rows(&nrows, bytes) != hipSuccess) {
+    if (hipMalloc(&nrows, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(RAMBO_ENOMEM, "rambo_fold: cannot allocate %llu bytes for the folded index",
                     (unsigned long long)bytes);
