@@ -4,7 +4,8 @@ eta from 1 to 16 (the generic row loop above 3), m not a power of two (the
 multiply-high range reduction), K not a multiple of 64 (result padding).
 Every shape: the whole index against the oracle's bits on sampled BFUs, and
 every read in both forms, every resolve strategy and schedule, with and
-without early exit, against the oracle."""
+without early exit, against the oracle, as bitsets and (scout schedule) as
+id lists."""
 import numpy as np
 import pytest
 
@@ -45,6 +46,9 @@ def test_unusual_shapes_bit_exact(shape):
     reads = gen.reads(dm, rm, 400)
     want, _ = o.query_seqs(reads.seqs, reads.offsets, oracle.MODE_ALG2, early_exit=True)
     assert want.any(axis=1).sum() > 10
+    want_bits = np.unpackbits(want.view(np.uint8), axis=1, bitorder="little")[:, :K]
+    want_ids = [np.nonzero(row)[0].tolist() for row in want_bits]
+    total = int(want_bits.sum())
     seqs, offs = reads_to_dev(reads)
     for mode in (rb.MODE_PLAIN, rb.MODE_BATCHED):
         idx.set_mode(mode)
@@ -59,6 +63,13 @@ def test_unusual_shapes_bit_exact(shape):
                     got = to_host_u64(idx.query_seqs(seqs, offs))
                     bad = np.nonzero((got != want).any(axis=1))[0]
                     assert bad.size == 0, (mode, resolve, ee, sched, bad[:5])
+                    if sched == 2:
+                        # id lists (in the batched form the scout pass then
+                        # walks each read one window per round)
+                        ids, id_off = idx.query_seqs_ids(seqs, offs, ids_cap=total)
+                        ids, id_off = ids.cpu().numpy(), id_off.cpu().numpy()
+                        for i in range(reads.n):
+                            assert ids[id_off[i]:id_off[i + 1]].tolist() == want_ids[i], (mode, resolve, ee, i)
     idx.set_early_exit(True)
     # single k-mer queries as well
     q, _ = gen.kmer_queries(dm, B + 2, 500, 0.5)
