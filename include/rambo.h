@@ -319,15 +319,17 @@ int rambo_query_term_sets(rambo_t *h, const uint64_t *terms, const uint64_t *off
 /* As rambo_query_seqs, but results are ascending document-id lists: read i's
  * ids are ids[id_offsets[i] .. id_offsets[i+1]) (device arrays, id_offsets
  * has n+1 entries, ids has room for ids_cap entries). Uses `scratch` (device,
- * n * W words) for the bitsets of non-empty answers: rows of reads with no id
- * are not written (their contents are unspecified afterwards), which spares
- * the bitset traffic of the many empty answers. Synchronous on `stream` (it
- * must learn the total). If the total exceeds ids_cap, returns RAMBO_ETRUNC
- * with id_offsets filled (id_offsets[n] = required capacity) and ids
- * untouched. Returns RAMBO_OK_EMPTYQ instead of RAMBO_OK if some read had no
- * valid window (its list holds every document). Calls on one handle are
- * serialised (a per-handle buffer holds the answer sizes, allocated or grown
- * by the call when n exceeds every earlier n). */
+ * n * W words) for the bitsets of non-empty answers, of which only the
+ * non-zero words are written (the rest of `scratch` is unspecified
+ * afterwards), which spares the bitset traffic of the many empty answers and
+ * empty words. Synchronous on `stream` (it must learn the total). If the
+ * total exceeds ids_cap, returns RAMBO_ETRUNC with id_offsets filled
+ * (id_offsets[n] = required capacity) and ids untouched. Returns
+ * RAMBO_OK_EMPTYQ instead of RAMBO_OK if some read had no valid window (its
+ * list holds every document). Calls on one handle are serialised (per-handle
+ * buffers hold the answer sizes and, per read, (W + 63) / 64 words marking
+ * its non-zero bitset words; allocated or grown by the call when n exceeds
+ * every earlier n). */
 int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64_t *offsets, uint64_t n,
                          uint64_t *scratch, uint32_t *ids, uint64_t *id_offsets, uint64_t ids_cap,
                          void *stream);

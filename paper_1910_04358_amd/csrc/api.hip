@@ -72,6 +72,7 @@ static void free_device(rambo_s *h) {
     if (h->d_cells) (void)hipFree(h->d_cells);
     if (h->d_cells0) (void)hipFree(h->d_cells0);
     if (h->d_ids_counts) (void)hipFree(h->d_ids_counts);
+    if (h->d_ids_wm) (void)hipFree(h->d_ids_wm);
     if (h->d_ids_aux) (void)hipFree(h->d_ids_aux);
     if (h->d_boff) (void)hipFree(h->d_boff);
     if (h->d_bdoc) (void)hipFree(h->d_bdoc);
@@ -441,11 +442,14 @@ RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64
     std::lock_guard<std::mutex> g(h->ids_mu);
     if (h->ids_counts_cap < n) {
         if (h->d_ids_counts) (void)hipFree(h->d_ids_counts);
+        if (h->d_ids_wm) (void)hipFree(h->d_ids_wm);
         if (h->d_ids_aux) (void)hipFree(h->d_ids_aux);
         h->d_ids_counts = nullptr;
+        h->d_ids_wm = nullptr;
         h->d_ids_aux = nullptr;
         h->ids_counts_cap = 0;
         HIP_CHECK(hipMalloc(&h->d_ids_counts, (n + 1) * 8));
+        HIP_CHECK(hipMalloc(&h->d_ids_wm, n * ((h->W + 63) / 64) * 8));
         HIP_CHECK(hipMalloc(&h->d_ids_aux, ids_aux_words(n) * 8));
         h->ids_counts_cap = n;
     }
@@ -453,11 +457,11 @@ RAMBO_API int rambo_query_seqs_ids(rambo_t *h, const uint8_t *seqs, const uint64
     int st = launch_store_u64(reinterpret_cast<uint64_t *>(h->d_ids_counts) + n, 0, s);  // reads without a term
     if (st != RAMBO_OK) return st;
     st = h->mode == RAMBO_MODE_BATCHED
-                 ? query_seqs_batched(h, seqs, offsets, n, scratch, s, h->d_ids_counts)
+                 ? query_seqs_batched(h, seqs, offsets, n, scratch, s, h->d_ids_counts, h->d_ids_wm)
                  : launch_query_seqs_plain(h, seqs, offsets, n, scratch, s, default_seg(h->RW), nullptr,
-                                           h->d_ids_counts);
+                                           h->d_ids_counts, h->d_ids_wm);
     if (st != RAMBO_OK) return st;
-    return launch_ids(h, scratch, n, ids, id_offsets, ids_cap, s, h->d_ids_counts, h->d_ids_aux);
+    return launch_ids(h, scratch, n, ids, id_offsets, ids_cap, s, h->d_ids_counts, h->d_ids_aux, h->d_ids_wm);
 }
 
 RAMBO_API int rambo_set_mode(rambo_t *h, int mode) {

@@ -44,7 +44,8 @@ struct BatchGraph {
 // Persistent batched form for batches described by in_dev (device; or, if
 // null, by an owned header set once to *init), up to cap reads.
 int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const InputHdr *init, uint64_t cap,
-                     uint64_t *out, std::shared_ptr<BatchGraph> &res, unsigned long long *counts = nullptr);
+                     uint64_t *out, std::shared_ptr<BatchGraph> &res, unsigned long long *counts = nullptr,
+                     uint64_t *wm = nullptr);
 // One-node graph of the plain kernel for batches described by in_dev.
 int make_plain_graph(rambo_s *h, const InputHdr *in_dev, uint64_t cap, uint64_t *out,
                      std::shared_ptr<BatchGraph> &res);

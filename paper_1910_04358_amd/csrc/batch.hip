@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
             if (ntiles == 1) {
                 // the whole read was in this tile: resolve from its masks
                 if (got == 0 && !scout_saw && lane == 0) atomicAdd(opt.emptyq, 1ULL);
-                answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, i);
+                answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, i, opt.wm);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 continue;
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 1 ? 1 
                     M[w] = __hip_atomic_fetch_or(rm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, i);
+                answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, i, opt.wm);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
@@ -487,7 +487,7 @@ static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
 }
 
 static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *out, hipStream_t s,
-                        unsigned long long *counts) {
+                        unsigned long long *counts, uint64_t *wm) {
     const Index ix = make_index(h);
     const uint32_t mw = h->R * h->RW;
     const int G = (int)h->RW / tu.seg;
@@ -495,7 +495,8 @@ static int enqueue_main(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
     const size_t lds = (size_t)tu.wpb * wave_lds(mw, h->W, use_res != 0, false).total * 4;
     // the scout schedule has run its scout windows in the scout pass already
     const int ksched = tu.sched == SCHED_SCOUT ? SCHED_PRESCOUT : tu.sched;
-    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, ksched, counts, counts ? counts + bg.cap : h->d_emptyq};
+    QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, ksched, counts, counts ? counts + bg.cap : h->d_emptyq,
+                  nullptr, counts ? wm : nullptr};
     // a persistent grid must be resident: never more workgroups than fit
 #define RAMBO_SPLIT_BODY_                                                                                  \
     {                                                                                                      \
@@ -583,7 +584,7 @@ static int alloc_graph_state(rambo_s *h, BatchGraph &bg, uint64_t cap, bool batc
 }
 
 int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const InputHdr *init, uint64_t cap,
-                     uint64_t *out, std::shared_ptr<BatchGraph> &res, unsigned long long *counts) {
+                     uint64_t *out, std::shared_ptr<BatchGraph> &res, unsigned long long *counts, uint64_t *wm) {
     auto bg = std::make_shared<BatchGraph>();
     bg->cap = cap;
     bg->tune = tu;
@@ -593,7 +594,7 @@ int make_batch_graph(rambo_s *h, const Tune &tu, const InputHdr *in_dev, const I
                      [&](hipStream_t s) { return enqueue_prep(h, tu, *bg, out, counts, s); });
     if (st == RAMBO_OK)
         st = capture(h, &bg->graph_main, &bg->exec_main,
-                     [&](hipStream_t s) { return enqueue_main(h, tu, *bg, out, s, counts); });
+                     [&](hipStream_t s) { return enqueue_main(h, tu, *bg, out, s, counts, wm); });
     if (st != RAMBO_OK) return st;
     res = bg;
     return RAMBO_OK;
@@ -624,26 +625,26 @@ int launch_batch_graph(rambo_s *h, BatchGraph &bg, hipStream_t s) {
 }
 
 static std::string graph_key(const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                             const unsigned long long *counts) {
-    char buf[256];
-    snprintf(buf, sizeof buf, "%p/%p/%llu/%p/%p/%d.%d.%d.%d.%d.%d", (const void *)seqs, (const void *)offs,
-             (unsigned long long)n, (void *)out, (const void *)counts, tu.seg, tu.tile, tu.waves_per_cu, tu.wpb,
-             tu.grab, tu.sched);
+                             const unsigned long long *counts, const uint64_t *wm) {
+    char buf[320];
+    snprintf(buf, sizeof buf, "%p/%p/%llu/%p/%p/%p/%d.%d.%d.%d.%d.%d", (const void *)seqs, (const void *)offs,
+             (unsigned long long)n, (void *)out, (const void *)counts, (const void *)wm, tu.seg, tu.tile,
+             tu.waves_per_cu, tu.wpb, tu.grab, tu.sched);
     return buf;
 }
 
 static int run_graph(rambo_s *h, const Tune &tu, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
-                     uint64_t *out, hipStream_t s, unsigned long long *counts = nullptr) {
+                     uint64_t *out, hipStream_t s, unsigned long long *counts = nullptr, uint64_t *wm = nullptr) {
     std::shared_ptr<BatchGraph> bg;
     std::lock_guard<std::mutex> g(h->mu);
-    const std::string key = graph_key(tu, seqs, offs, n, out, counts);
+    const std::string key = graph_key(tu, seqs, offs, n, out, counts, wm);
     auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         bg = it->second;
     } else {
         if (h->graphs.size() >= 16) h->graphs.clear();
         const InputHdr init{n, offs, seqs, 0};
-        int st = make_batch_graph(h, tu, nullptr, &init, n, out, bg, counts);
+        int st = make_batch_graph(h, tu, nullptr, &init, n, out, bg, counts, wm);
         if (st != RAMBO_OK) return st;
         h->graphs[key] = bg;
     }
@@ -787,7 +788,7 @@ int autotune(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, 
 }
 
 int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                       hipStream_t s, unsigned long long *counts) {
+                       hipStream_t s, unsigned long long *counts, uint64_t *wm) {
     if (!h->tuned) {
         h->tune.seg = default_seg(h->RW);
         const char *mode = getenv("RAMBO_TUNE");
@@ -804,7 +805,7 @@ int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, ui
         std::lock_guard<std::mutex> g(h->mu);
         tu = h->tune;
     }
-    return run_graph(h, tu, seqs, offs, n, out, s, counts);
+    return run_graph(h, tu, seqs, offs, n, out, s, counts, wm);
 }
 
 }  // namespace rambo

@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_query_seqs_plain(Index ix, const uint8_
     uint64_t *o = out + read * ix.W;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, read);
+    answer_read(ix, M, res, o, lane, opt.rmode, opt.counts, read, opt.wm);
 }
 
 // -------------------------------------------------------------------------
@@ -298,7 +298,7 @@ int launch_query_kmers(rambo_s *h, const uint64_t *kmers, uint64_t n, uint64_t *
 }
 
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                            hipStream_t s, int seg, const InputHdr *hdr, unsigned long long *counts) {
+                            hipStream_t s, int seg, const InputHdr *hdr, unsigned long long *counts, uint64_t *wm) {
     // with hdr, the batch is read on the device and n is only its capacity
     const Index ix = make_index(h);
     const int G = (int)h->RW / seg;
@@ -312,7 +312,7 @@ int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *off
     // id-list mode counts queries without a term in the word after the n
     // answer sizes (the caller zeroes it), bitset mode in the handle
     QueryOpts opt{h->resolve, h->early_exit, h->probe_counter, sched, counts, counts ? counts + n : h->d_emptyq,
-                  h->sparse_counter};
+                  h->sparse_counter, counts ? wm : nullptr};
     // the RAMBO+ tallies have a kernel of their own (measurement only)
 #define RAMBO_SPLIT_BODY_                                                                                  \
     if (opt.rplus)                                                                                         \
@@ -403,6 +403,54 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ bi
     }
 }
 
+// As k_compact, reading only the words the query marked non-zero in wm
+// ((W + 63) / 64 words per read): per mark word, the lanes take its 64
+// bitset words, load the marked ones, and number their ids by a prefix sum,
+// mark words in order, so each read's ids come out ascending.
+__global__ __launch_bounds__(256) void k_compact_marked(const uint64_t *__restrict__ bits,
+                                                        const uint64_t *__restrict__ wm, uint64_t n, uint32_t W,
+                                                        const uint64_t *__restrict__ off, uint32_t *__restrict__ ids,
+                                                        uint64_t cap) {
+    const uint32_t lane = threadIdx.x & 63, WM = (W + 63) / 64;
+    const uint64_t i0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
+    if (i0 >= n || off[n] > cap) return;
+    const uint64_t mine = i0 + lane;
+    uint64_t todo = __ballot(mine < n && off[mine + 1] != off[mine]);
+    while (todo) {
+        const uint64_t i = i0 + (uint64_t)__builtin_ctzll(todo);
+        todo &= todo - 1;
+        const uint64_t *row = bits + i * W, *marks = wm + i * WM;
+        uint64_t base = off[i];
+        for (uint32_t m0 = 0; m0 < WM; m0 += 64) {
+            const uint64_t mw = m0 + lane < WM ? marks[m0 + lane] : 0;
+            uint64_t src = __ballot(mw != 0);
+            while (src) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(src);
+                src &= src - 1;
+                // (readlane returns a signed int: widen through uint32_t)
+                const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mw >> 32), (int)j) << 32) |
+                                   (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mw, (int)j);
+                const uint32_t w = (m0 + j) * 64 + lane;
+                const uint64_t v = (((m >> lane) & 1) && w < W) ? row[w] : 0;
+                const uint32_t pc = (uint32_t)__popcll(v);
+                uint32_t incl = pc;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t t = __shfl_up(incl, d);
+                    if ((int)lane >= d) incl += t;
+                }
+                uint64_t pos = base + incl - pc;
+                uint64_t x = v;
+                while (x) {
+                    ids[pos++] = w * 64 + (uint32_t)__builtin_ctzll(x);
+                    x &= x - 1;
+                }
+                base += __shfl(incl, 63);
+            }
+        }
+    }
+}
+
 __global__ void k_store_u64(uint64_t *p, uint64_t v) {
     if (threadIdx.x == 0) *p = v;
 }
@@ -410,7 +458,7 @@ __global__ void k_store_u64(uint64_t *p, uint64_t v) {
 uint64_t ids_aux_words(uint64_t n) { return scan_parts_needed(n) + 1; }
 
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off, uint64_t ids_cap,
-               hipStream_t s, const unsigned long long *counts, uint64_t *aux) {
+               hipStream_t s, const unsigned long long *counts, uint64_t *aux, const uint64_t *wm) {
     const uint32_t W = (uint32_t)h->W;
     uint64_t total = 0;
     if (n == 0) {
@@ -427,8 +475,12 @@ int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint
     // to the host before it
     if (ids) {
         const uint64_t waves = (n + 63) / 64;
-        hipLaunchKernelGGL(k_compact, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, bits, n, W, id_off, ids,
-                           ids_cap);
+        if (wm)
+            hipLaunchKernelGGL(k_compact_marked, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, bits, wm, n, W,
+                               id_off, ids, ids_cap);
+        else
+            hipLaunchKernelGGL(k_compact, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, bits, n, W, id_off,
+                               ids, ids_cap);
         HIP_CHECK(hipGetLastError());
     }
     unsigned long long noterm = 0;

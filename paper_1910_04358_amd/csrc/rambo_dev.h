@@ -990,7 +990,10 @@ __device__ __forceinline__ bool doc_kept(const Index &ix, const uint32_t *M, con
 // Dense: every document tests its R cells; lane l handles document 64 w + l
 // and a ballot forms result word w. Eight words' cell records are loaded
 // together.
-__device__ __forceinline__ uint64_t resolve_dense(const Index &ix, const uint32_t *M, uint64_t *out, uint32_t lane) {
+// With wm (id-list mode), only the non-zero words are written, and wm[k]
+// marks which of words 64 k .. 64 k + 63 those are.
+__device__ __forceinline__ uint64_t resolve_dense(const Index &ix, const uint32_t *M, uint64_t *out, uint32_t lane,
+                                                  uint64_t *wm) {
     constexpr uint32_t U = 8;
     uint64_t pc = 0;  // this lane's documents kept
     for (uint32_t w0 = 0; w0 < ix.W; w0 += 64) {
@@ -1011,8 +1014,12 @@ __device__ __forceinline__ uint64_t resolve_dense(const Index &ix, const uint32_
                 if (lane == t + u) mine = word;
             }
         }
+        if (wm) {
+            const uint64_t nz = __ballot(lane < nw && mine != 0);
+            if (lane == 0) wm[w0 >> 6] = nz;
+        }
         if (lane < nw) {
-            out[w0 + lane] = mine;
+            if (!wm || mine) out[w0 + lane] = mine;
             pc += (uint64_t)__popcll(mine);
         }
     }
@@ -1028,7 +1035,7 @@ __device__ __forceinline__ uint64_t resolve_dense(const Index &ix, const uint32_
 // loads, the document ids and their cell records each take one round trip
 // for up to 128 candidates.
 __device__ __forceinline__ uint64_t resolve_candidates(const Index &ix, const uint32_t *M, uint64_t *res,
-                                                       uint64_t *out, uint32_t lane) {
+                                                       uint64_t *out, uint32_t lane, uint64_t *wm) {
     for (uint32_t w = lane; w < ix.W; w += 64) res[w] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1085,9 +1092,14 @@ __device__ __forceinline__ uint64_t resolve_candidates(const Index &ix, const ui
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     uint64_t pc = 0;
-    for (uint32_t w = lane; w < ix.W; w += 64) {
-        const uint64_t v = res[w];
-        out[w] = v;
+    for (uint32_t w0 = 0; w0 < ix.W; w0 += 64) {
+        const uint32_t w = w0 + lane;
+        const uint64_t v = w < ix.W ? res[w] : 0;
+        if (wm) {
+            const uint64_t nz = __ballot(v != 0);
+            if (lane == 0) wm[w0 >> 6] = nz;
+        }
+        if (w < ix.W && (!wm || v)) out[w] = v;
         pc += (uint64_t)__popcll(v);
     }
     return pc;
@@ -1100,8 +1112,10 @@ __device__ __forceinline__ uint64_t resolve_candidates(const Index &ix, const ui
 // (the documents of distinct cells are distinct, so each bit is set once).
 // Returns this lane's number of documents kept.
 __device__ __forceinline__ uint64_t resolve_candidates_out(const Index &ix, const uint32_t *M, uint64_t *out,
-                                                           uint32_t lane) {
+                                                           uint32_t lane, uint64_t *wm) {
     for (uint32_t w = lane; w < ix.W; w += 64) out[w] = 0;
+    if (wm)
+        for (uint32_t k = lane; k < (ix.W + 63) / 64; k += 64) wm[k] = 0;
     // every lane's zeros are performed (acknowledged by L2) before any OR
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
@@ -1149,6 +1163,7 @@ __device__ __forceinline__ uint64_t resolve_candidates_out(const Index &ix, cons
             for (int u = 0; u < U; u++)
                 if (has[u] && doc_kept<1>(ix, M, cd[u])) {
                     atomicOr((unsigned long long *)&out[d[u] >> 6], 1ULL << (d[u] & 63));
+                    if (wm) atomicOr((unsigned long long *)&wm[d[u] >> 12], 1ULL << ((d[u] >> 6) & 63));
                     kept++;
                 }
         }
@@ -1168,13 +1183,13 @@ __device__ __forceinline__ uint64_t estimate_candidates(const Index &ix, const u
 // the candidates collect there; without, straight in the output row).
 // Returns the number of documents reported (wave-uniform).
 __device__ __forceinline__ uint64_t resolve(const Index &ix, const uint32_t *M, uint64_t *res, uint64_t *out,
-                                            uint32_t lane, int mode) {
+                                            uint32_t lane, int mode, uint64_t *wm = nullptr) {
     bool cand = false;
     if (mode == 2) cand = true;
     else if (mode == 0) cand = estimate_candidates(ix, M) * (ix.R - 1) * 2 < ix.K * ix.R;
-    uint64_t pc = !cand              ? resolve_dense(ix, M, out, lane)
-                  : res != nullptr ? resolve_candidates(ix, M, res, out, lane)
-                                   : resolve_candidates_out(ix, M, out, lane);
+    uint64_t pc = !cand              ? resolve_dense(ix, M, out, lane, wm)
+                  : res != nullptr ? resolve_candidates(ix, M, res, out, lane, wm)
+                                   : resolve_candidates_out(ix, M, out, lane, wm);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off);
     return pc;
@@ -1187,9 +1202,12 @@ __device__ __forceinline__ void write_zeros(uint64_t *out, uint32_t W, uint32_t 
 
 // Answer of a read whose masks are final: with counts (id-list mode) an
 // empty answer writes only its count (the bitset row is left as it is) and
-// a non-empty one its bitset and count; otherwise the bitset row always.
+// a non-empty one its bitset and count, and with wm as well (per read,
+// (W + 63) / 64 words) only the bitset's non-zero words and their marks;
+// otherwise the bitset row always.
 __device__ __forceinline__ void answer_read(const Index &ix, const uint32_t *M, uint64_t *res, uint64_t *o,
-                                            uint32_t lane, int mode, unsigned long long *counts, uint64_t i) {
+                                            uint32_t lane, int mode, unsigned long long *counts, uint64_t i,
+                                            uint64_t *wm = nullptr) {
     if (masks_some_rep_empty(ix, M, lane)) {
         if (counts) {
             if (lane == 0) counts[i] = 0;
@@ -1198,7 +1216,8 @@ __device__ __forceinline__ void answer_read(const Index &ix, const uint32_t *M, 
         }
         return;
     }
-    const uint64_t pc = resolve(ix, M, res, o, lane, mode);
+    uint64_t *wrow = (counts && wm) ? wm + i * ((ix.W + 63) / 64) : nullptr;
+    const uint64_t pc = resolve(ix, M, res, o, lane, mode, wrow);
     if (counts && lane == 0) counts[i] = pc;
 }
 

@@ -57,6 +57,7 @@ struct rambo_s {
     // id-list queries: per-read answer sizes and scan scratch (grown as
     // needed; one id-list query at a time per handle)
     unsigned long long *d_ids_counts = nullptr;
+    uint64_t *d_ids_wm = nullptr;  // [ids_counts_cap][(W + 63) / 64] non-zero word marks
     uint64_t *d_ids_aux = nullptr;
     uint64_t ids_counts_cap = 0;
     std::mutex ids_mu;
@@ -110,6 +111,8 @@ struct QueryOpts {
     unsigned long long *counts;   // id-list mode: per-read answer sizes, zero answers not written; or null
     unsigned long long *emptyq;   // incremented once per query that has no term (no valid window)
     unsigned long long *rplus;    // RAMBO+ tallies (plain form, sweep/scout schedules), or null
+    uint64_t *wm;                 // id-list mode: per read, (W + 63) / 64 words whose bit j of word k marks
+                                  // bitset word 64 k + j non-zero (only non-zero words are then written); or null
 };
 
 // api.hip: create an index (gids: null, or K global document ids of a shard)
@@ -135,20 +138,22 @@ int launch_query_termsets(rambo_s *h, const uint64_t *terms, const uint64_t *off
 // the capacity the grid is sized for. With counts, id-list mode (QueryOpts).
 int launch_query_seqs_plain(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n,
                             uint64_t *out, hipStream_t s, int seg, const InputHdr *hdr = nullptr,
-                            unsigned long long *counts = nullptr);
+                            unsigned long long *counts = nullptr, uint64_t *wm = nullptr);
 // Bitsets of an id-list mode query to id lists: counts holds the n answer
 // sizes the query wrote, aux ids_aux_words(n) words of scan scratch.
 uint64_t ids_aux_words(uint64_t n);
 // counts has n + 1 words: the answer sizes, then the number of reads without
 // a term (RAMBO_OK_EMPTYQ is returned if it is not zero).
+// With wm (the query's non-zero word marks), only the marked words are read.
 int launch_ids(rambo_s *h, const uint64_t *bits, uint64_t n, uint32_t *ids, uint64_t *id_off,
-               uint64_t ids_cap, hipStream_t s, const unsigned long long *counts, uint64_t *aux);
+               uint64_t ids_cap, hipStream_t s, const unsigned long long *counts, uint64_t *aux,
+               const uint64_t *wm = nullptr);
 // *p = v on stream s (a one-thread kernel: no memset node in captured work)
 int launch_store_u64(uint64_t *p, uint64_t v, hipStream_t s);
 
 // batch.hip
 int query_seqs_batched(rambo_s *h, const uint8_t *seqs, const uint64_t *offs, uint64_t n, uint64_t *out,
-                       hipStream_t s, unsigned long long *counts = nullptr);
+                       hipStream_t s, unsigned long long *counts = nullptr, uint64_t *wm = nullptr);
 void drop_graphs(rambo_s *h);
 
 // Row split: a lane reads SEG words of a row, G = row_words / SEG lanes share
