@@ -43,52 +43,75 @@ __global__ void k_batch_reset(BatchBufs bb) {
 // With a scout pass before it (prescout), reads that pass ended are
 // answered already and left out of the queue, and a multi-tile read's
 // running mask starts from its scout AND in repetition 0.
+// Each thread takes kPrepReads reads (256 apart), so a workgroup makes one
+// atomic per size class for 256 x kPrepReads reads: same-address atomics
+// serialise, and one per 256 reads made the pass over 10^6 reads wait on them
+// (52 -> 23 us with 4); small batches keep one read per thread (100,000
+// reads: 9 us with 1, 19 us with 4, where fewer workgroups wait longer).
+template <uint32_t kPrepReads>
 __global__ __launch_bounds__(256) void k_batch_prep(const InputHdr *in, uint32_t mw, uint32_t rw, uint32_t tile,
                                                     BatchBufs bb, int prescout) {
     const uint64_t n = in->n;
     const uint64_t *__restrict__ offs = in->offs;
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t lane = threadIdx.x & 63;
-    bool real = i < n;
-    uint32_t cls = 0;
-    if (real && prescout && !(bb.live[i] & 1u)) {
-        bb.extra[i] = 0;
-        real = false;
-    } else if (real) {
-        const uint64_t beg = offs[i], end = offs[i + 1];
-        const uint64_t nw = n_windows(beg, end > beg ? end : beg);
-        const uint64_t tiles = nw ? (nw + tile - 1) / tile : 1;
-        bb.extra[i] = tiles - 1;
-        if (tiles > 1) {
-            bb.done[i] = 0;
-            for (uint32_t w = 0; w < mw; w++)
-                bb.rmask[i * mw + w] = (prescout && w < rw) ? bb.smask[i * rw + w] : 0xFFFFFFFFu;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool real[kPrepReads];
+    uint32_t cls[kPrepReads];
+#pragma unroll
+    for (uint32_t k = 0; k < kPrepReads; k++) {
+        const uint64_t i = ((uint64_t)blockIdx.x * kPrepReads + k) * blockDim.x + threadIdx.x;
+        real[k] = i < n;
+        cls[k] = 0;
+        if (real[k] && prescout && !(bb.live[i] & 1u)) {
+            bb.extra[i] = 0;
+            real[k] = false;
+        } else if (real[k]) {
+            const uint64_t beg = offs[i], end = offs[i + 1];
+            const uint64_t nw = n_windows(beg, end > beg ? end : beg);
+            const uint64_t tiles = nw ? (nw + tile - 1) / tile : 1;
+            bb.extra[i] = tiles - 1;
+            if (tiles > 1) {
+                bb.done[i] = 0;
+                for (uint32_t w = 0; w < mw; w++)
+                    bb.rmask[i * mw + w] = (prescout && w < rw) ? bb.smask[i * rw + w] : 0xFFFFFFFFu;
+            }
+            cls[k] = (uint32_t)min<uint64_t>(3, min<uint64_t>(nw, tile) * 4 / tile);
         }
-        cls = (uint32_t)min<uint64_t>(3, min<uint64_t>(nw, tile) * 4 / tile);
     }
-    // slots in the class lists: ranks within the wave (ballots), wave
-    // offsets within the workgroup (LDS), one atomic per class and workgroup
-    __shared__ uint32_t wcount[4][4];  // [wave][class]
+    // slots in the class lists, in read order: ranks within the wave
+    // (ballots), offsets of the earlier (read group, wave) pairs of the
+    // workgroup (LDS), one atomic per class and workgroup
+    __shared__ uint32_t wcount[kPrepReads][4][4];  // [read group][wave][class]
     __shared__ unsigned long long bbase[4];
-    const uint32_t wave = threadIdx.x >> 6;
-    uint64_t mine = 0;
-    for (uint32_t v = 0; v < 4; v++) {
-        const uint64_t mask = __ballot(real && cls == v);
-        if (cls == v) mine = mask;
-        if (lane == 0) wcount[wave][v] = (uint32_t)__popcll(mask);
+    uint64_t mine[kPrepReads];
+#pragma unroll
+    for (uint32_t k = 0; k < kPrepReads; k++) {
+        mine[k] = 0;
+        for (uint32_t v = 0; v < 4; v++) {
+            const uint64_t mask = __ballot(real[k] && cls[k] == v);
+            if (cls[k] == v) mine[k] = mask;
+            if (lane == 0) wcount[k][wave][v] = (uint32_t)__popcll(mask);
+        }
     }
     __syncthreads();
+    const uint32_t waves = blockDim.x >> 6;
     if (threadIdx.x < 4) {
         const uint32_t v = threadIdx.x;
         uint32_t tot = 0;
-        for (uint32_t k = 0; k < (blockDim.x >> 6); k++) tot += wcount[k][v];
+        for (uint32_t k = 0; k < kPrepReads; k++)
+            for (uint32_t w = 0; w < waves; w++) tot += wcount[k][w][v];
         bbase[v] = tot ? atomicAdd(bb.cls + 16 * v, (unsigned long long)tot) : 0ull;
     }
     __syncthreads();
-    if (real) {
-        uint64_t slot = bbase[cls] + __popcll(mine & ((1ULL << lane) - 1));
-        for (uint32_t k = 0; k < wave; k++) slot += wcount[k][cls];
-        bb.order[(uint64_t)cls * bb.cap + slot] = (uint32_t)i;
+#pragma unroll
+    for (uint32_t k = 0; k < kPrepReads; k++) {
+        if (!real[k]) continue;
+        const uint32_t c = cls[k];
+        uint64_t slot = bbase[c] + __popcll(mine[k] & ((1ULL << lane) - 1));
+        for (uint32_t kk = 0; kk < k; kk++)
+            for (uint32_t w = 0; w < waves; w++) slot += wcount[kk][w][c];
+        for (uint32_t w = 0; w < wave; w++) slot += wcount[k][w][c];
+        const uint64_t i = ((uint64_t)blockIdx.x * kPrepReads + k) * blockDim.x + threadIdx.x;
+        bb.order[(uint64_t)c * bb.cap + slot] = (uint32_t)i;
     }
 }
 
@@ -479,8 +502,14 @@ static int enqueue_prep(rambo_s *h, const Tune &tu, BatchGraph &bg, uint64_t *ou
 #undef RAMBO_SPLIT_BODY_
         HIP_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, bg.in, mw, h->RW,
-                       (uint32_t)tu.tile, bg.bb, pre ? 1 : 0);
+    // four reads per thread once one per thread would take over eight
+    // workgroups per compute unit
+    if ((bg.cap + 255) / 256 > 8 * (uint64_t)h->n_cu)
+        hipLaunchKernelGGL(k_batch_prep<4>, dim3((unsigned)((bg.cap + 1023) / 1024)), dim3(256), 0, s, bg.in, mw,
+                           h->RW, (uint32_t)tu.tile, bg.bb, pre ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_batch_prep<1>, dim3((unsigned)((bg.cap + 255) / 256)), dim3(256), 0, s, bg.in, mw,
+                           h->RW, (uint32_t)tu.tile, bg.bb, pre ? 1 : 0);
     HIP_CHECK(hipGetLastError());
     // the header's first field is n
     return launch_exclusive_scan(bg.bb.extra, &bg.in->n, bg.cap, bg.bb.extra_off, bg.parts, s);

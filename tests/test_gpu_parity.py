@@ -261,6 +261,35 @@ def test_scout_pass_many_reads_per_lane_group(name):
     idx.set_mode(rb.MODE_PLAIN)
 
 
+def test_large_batch_queue_building():
+    """A batch of 600,000 reads, enough that the batched form's queue building
+    takes four reads per thread (one atomic per size class for 1,024 reads):
+    its bitsets and id lists equal the plain form's, which the other tests
+    hold to the oracle, and a seeded sample of reads equals the oracle's."""
+    idx, o, dm, reads, want = setup_case("rw4")
+    rm = gen.ReadModel(qseed=4321, src_lo=0, src_hi=dm.n_docs, len_kind=1, lo=31, hi=200, err_lo=0.0,
+                       err_hi=0.01)
+    big = gen.reads(dm, rm, 600_000)
+    seqs, offs = reads_to_dev(big)
+    idx.set_mode(rb.MODE_PLAIN)
+    plain = to_host_u64(idx.query_seqs(seqs, offs))
+    total = int(np.bitwise_count(plain).sum())
+    assert total > 100_000
+    p_ids, p_off = idx.query_seqs_ids(seqs, offs, ids_cap=total)
+    idx.set_mode(rb.MODE_BATCHED)
+    idx.set_tune(rb.Tune(4, 1024, 16, 4, 1, 2))
+    got = to_host_u64(idx.query_seqs(seqs, offs))
+    assert np.array_equal(got, plain)
+    ids, id_off = idx.query_seqs_ids(seqs, offs, ids_cap=total)
+    assert np.array_equal(id_off.cpu().numpy(), p_off.cpu().numpy())
+    assert np.array_equal(ids.cpu().numpy(), p_ids.cpu().numpy())
+    sample = np.random.default_rng(4322).choice(big.n, 300, replace=False)
+    hs, ho = make_reads([big.read(int(i)) for i in sample])
+    want_s, _ = o.query_seqs(hs, ho, oracle.MODE_ALG2, early_exit=True)
+    assert np.array_equal(got[sample], want_s)
+    idx.set_mode(rb.MODE_PLAIN)
+
+
 def test_invalid_kmer_values_reported():
     idx, o, dm, reads, want = setup_case("rw1")
     q = np.array([5, 1 << 62, 7, (1 << 64) - 1], dtype=np.uint64)
